@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the HIP Swendsen-Wang sweep on one MI355X.
+
+Workload: Ising model on the periodic pyrochlore lattice, L = 128
+(33,554,432 sites, 100,663,296 bonds), int8 spins and int32 labels, five
+lattices resident at T = 4.205, 4.210, 4.2139, 4.218, 4.223 (seeds 1..5,
+random start).  One step = one Swendsen-Wang sweep of each of the five
+lattices (bond activation, cluster labeling, cluster flips, moments);
+--steps 10000 is the full five-temperature run.
+
+Printed on one JSON line: spin-updates/s over the timed steps, the roofline
+of the dominant kernel (algorithmic bytes per launch / its mean duration,
+timed with HIP events on the stream it runs on), and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SW spin-updates/sec and % HBM roofline, Ising L=128; batched vs plain, p99 job latency"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+# Algorithmic HBM bytes per site of one launch of each Ising kernel (each
+# array element read or written once; halo re-reads and L2/MALL hits not
+# counted).  Per-cell arrays are spread over the cell's 16 sites.
+BYTES_PER_SITE = {
+    "bonds": 1.0 + 4.0 + 8.0 / 16,    # read spins, write identity labels, write 48-bit masks
+    "union": 8.0 / 16 + 4.0,          # read masks, touch labels of bond ends
+    "flip_table": 1.0 / 8,            # write one flip bit per site
+    "flip": 4.0 + 4.0 + 1.0 + 1.0,    # read/write labels, read/write spins
+    "energy": 1.0,                    # read spins
+    "finalize": 0.0,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(L, T, seed, sweeps):
+    """Time the CPU oracle (single thread) on `sweeps` sweeps of one L
+    lattice at temperature T; lattice construction is not timed."""
+    import oracle
+
+    o = oracle.Oracle(L=L, model=oracle.ISING, T=T, seed=seed, start=oracle.RANDOM)
+    t0 = time.perf_counter()
+    o.sweep(sweeps)
+    dt = time.perf_counter() - t0
+    return dict(value=o.N * sweeps / dt, unit="spin-updates/s", cores=1, kind="oracle",
+                sample=f"{sweeps} sweeps of one Ising L={L} lattice at T={T} (N={o.N}), "
+                       f"random start, single-threaded C oracle, lattice build not timed")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--L", type=int, default=128)
+    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for cpu_baseline (0: skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent lattices would shard by replica; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    cfg = workloads.ISING_L128
+    L = args.L
+    temps, seeds = cfg["temps"], cfg["seeds"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    log(f"bench: building {len(temps)} Ising L={L} lattices")
+    lats = [pyrosw.Lattice(L=L, model=1, T=T, seed=s, start=cfg["start"], device=dev, stream=stream)
+            for T, s in zip(temps, seeds)]
+    N = lats[0].N
+
+    # Find the dominant kernel over a few timed sweeps.
+    for lt in lats:
+        pyrosw.pyro_sw_set_timing(lt.h, -1)
+    for _ in range(max(1, min(args.warmup, 5))):
+        for lt in lats:
+            lt.sweep(1)
+    kt = {}
+    for lt in lats:
+        for k, (n, ms) in pyrosw.pyro_sw_kernel_times(lt.h).items():
+            a = kt.setdefault(k, [0, 0.0])
+            a[0] += n
+            a[1] += ms
+    names = list(kt)
+    dominant = max(kt, key=lambda k: kt[k][1])
+    log("bench: kernel shares over probe sweeps:",
+        {k: round(v[1] / max(v[0], 1), 4) for k, v in kt.items() if v[0]})
+
+    # Warmup, then the timed region with HIP events on the dominant kernel only.
+    for _ in range(args.warmup):
+        for lt in lats:
+            lt.sweep(1)
+    for lt in lats:
+        lt.moments()  # discard warmup records
+        pyrosw.pyro_sw_set_timing(lt.h, 1 << names.index(dominant))
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for lt in lats:
+            lt.sweep(1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dom_n, dom_ms = 0, 0.0
+    for lt in lats:
+        n, ms = pyrosw.pyro_sw_kernel_times(lt.h)[dominant]
+        dom_n += n
+        dom_ms += ms
+    recs = [lt.moments() for lt in lats]
+    for lt in lats:
+        lt.close()
+
+    updates = N * len(lats) * args.steps
+    value = updates / dt
+    dom_avg_s = dom_ms / max(dom_n, 1) / 1e3
+    bytes_per_launch = BYTES_PER_SITE.get(dominant, 0.0) * N
+    achieved = bytes_per_launch / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
+    binder = {}
+    for T, r in zip(temps, recs):
+        half = r[len(r) // 2:]
+        if len(half):
+            binder[str(T)] = float(np.mean(half["m4"]) / np.mean(half["m2"]) ** 2)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"ising_pyrochlore_L{L}_5T",
+            "L": L,
+            "sites_per_lattice": N,
+            "lattices": len(lats),
+            "temperatures": list(temps),
+            "seeds": list(seeds),
+            "start": "random",
+            "sweeps_per_lattice": args.steps,
+            "step": "one SW sweep of each lattice",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "alg_bytes_per_site": BYTES_PER_SITE.get(dominant, 0.0),
+            "mean_launch_us": dom_avg_s * 1e6,
+        },
+        "sweep_alg_roofline_frac": value * 11.0 / (HBM_PEAK_GBS * 1e9),
+        "binder_U_second_half": binder,
+        "kernel_mean_us": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},
+    }
+    if args.cpu_sweeps > 0:
+        log("bench: timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(L, temps[2], seeds[2], args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * pyro_sw.h -- C ABI of the MI355X (gfx950) Swendsen-Wang library for the
+ * ferromagnetic O(n) model on the periodic pyrochlore lattice.
+ *
+ * Method: Soldatov, Nefedev, Komura, Okabe, "Large-scale calculation of
+ * ferromagnetic spin systems on the pyrochlore lattice".
+ *   - lattice: 16-site cubic unit cell, L x L x L cells, periodic, N = 16 L^3
+ *     sites, coordination six (Sec. 2);
+ *   - model: H = -J sum_<ij> s_i . s_j with unit n-vectors, n = 1 (Ising),
+ *     2 (XY), 3 (Heisenberg) (Sec. 2, Eq. 1);
+ *   - update: Swendsen-Wang multi-cluster flips, with Wolff's embedded-cluster
+ *     idea for n = 2, 3 (Sec. 1, Sec. 2);
+ *   - measurement: M, m = M/N, m^2 and m^4 per sweep for the moment ratio
+ *     U = <m^4>/<m^2>^2 (Sec. 3.1, Eq. 2), and E = H.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns PYRO_OK (0) or a negative pyro_status; the text of
+ *     the last error on the calling thread is pyro_sw_last_error().
+ *   - A handle is not thread-safe: calls on one handle must be serialised.
+ *     Distinct handles are independent.
+ *   - pyro_sw_sweep only enqueues work on the handle's HIP stream;
+ *     pyro_sw_moments, pyro_sw_get_* and pyro_sw_destroy synchronise it.
+ *   - Host buffers always belong to the caller.  Device memory passed to
+ *     pyro_sw_init_ext belongs to the caller and must outlive the handle.
+ *   - After a HIP error a handle returns PYRO_ESTATE from every call except
+ *     pyro_sw_destroy.
+ *   - Results are a deterministic function of (L, model, T, J, seed, start,
+ *     sweep index): cluster labels are the smallest site index of each
+ *     cluster and every random draw is keyed by (seed, sweep, stream, unit),
+ *     so the trajectory does not depend on launch order or tiling.
+ *
+ * Site numbering: cell (x, y, z) has index (z*L + y)*L + x; site (cell, f,
+ * mu) has index 16*cell + 4*f + mu, at position 4*(x,y,z) + F_f + B_mu in
+ * units of a/4, with FCC points F = (0,0,0), (0,2,2), (2,0,2), (2,2,0) and
+ * tetrahedral basis B = (0,0,0), (0,1,1), (1,0,1), (1,1,0).
+ */
+#ifndef PYRO_SW_H
+#define PYRO_SW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pyro_sw pyro_sw;
+
+/* Model = number of spin components n (Sec. 2, Eq. 1). */
+enum { PYRO_ISING = 1, PYRO_XY = 2, PYRO_HEISENBERG = 3 };
+
+/* Initial state: all spins +1 (Ising) or (1, 0, 0) (O(n)); or drawn from the
+ * INIT random stream (independent uniform signs / unit vectors). */
+enum { PYRO_START_COLD = 0, PYRO_START_RANDOM = 1 };
+
+typedef enum {
+    PYRO_OK = 0,
+    PYRO_EINVAL = -1, /* an argument is out of range */
+    PYRO_ENOMEM = -2, /* device or host allocation failed */
+    PYRO_EDEVICE = -3, /* a HIP call failed; the handle is now unusable */
+    PYRO_ESTATE = -4   /* the handle failed earlier, or a call is out of order */
+} pyro_status;
+
+/* One record per sweep, describing the state after that sweep (Eq. 1, Eq. 2). */
+typedef struct {
+    int64_t sweep;    /* global 0-based index of the sweep */
+    int64_t bond_sum; /* Ising: sum over the 3N bonds of s_i s_j, exact; O(n): 0 */
+    int64_t M_int;    /* Ising: sum of s_i, exact; O(n): 0 */
+    int64_t reserved;
+    double E;         /* energy -J sum_<ij> s_i . s_j (O(n): FP64 sum of FP32 spins) */
+    double M[3];      /* magnetisation vector sum_i s_i (Ising: M[0] = M_int) */
+    double m2;        /* m*m with m = |M| / N */
+    double m4;        /* m2*m2 */
+} pyro_sw_record;
+
+/*
+ * Create a simulation of one lattice.
+ *   L      number of cubic cells per edge, 1 <= L <= 447 (so that N < 2^31 and
+ *          3N < 2^32);
+ *   model  PYRO_ISING, PYRO_XY or PYRO_HEISENBERG;
+ *   T      temperature in units of J/k_B, T > 0; T = +inf is accepted (no bond
+ *          is ever activated);
+ *   J      coupling, 0 < J < inf (ferromagnet);
+ *   seed   64-bit key of every random stream;
+ *   start  PYRO_START_COLD or PYRO_START_RANDOM;
+ *   stream a hipStream_t on which all work is enqueued, or NULL for a stream
+ *          the handle creates and owns.
+ * All device memory is allocated by the library and freed by destroy.
+ * Errors: PYRO_EINVAL (arguments), PYRO_ENOMEM, PYRO_EDEVICE.
+ */
+int pyro_sw_init(pyro_sw **out, int L, int model, double T, double J, uint64_t seed,
+                 int start, void *stream);
+
+/*
+ * Device memory needed by pyro_sw_init_ext for (L, model): spin_bytes for the
+ * spin array (Ising: int8 [N]; O(n): float [n][N], component-major) and
+ * work_bytes for everything else.  Both are multiples of 256.
+ */
+int pyro_sw_workspace_size(int L, int model, size_t *spin_bytes, size_t *work_bytes);
+
+/*
+ * As pyro_sw_init, but the spin array and the workspace are caller-owned
+ * device memory (for example tensors allocated by PyTorch), 256-byte aligned,
+ * of at least the sizes pyro_sw_workspace_size returns.  The library writes
+ * the initial state into dev_spins.  Errors as pyro_sw_init, plus
+ * PYRO_EINVAL for NULL, misaligned or too small buffers.
+ */
+int pyro_sw_init_ext(pyro_sw **out, int L, int model, double T, double J, uint64_t seed,
+                     int start, void *stream, void *dev_spins, size_t spin_bytes,
+                     void *dev_work, size_t work_bytes);
+
+/*
+ * Enqueue n_sweeps >= 0 Swendsen-Wang sweeps (bond activation, cluster
+ * labeling, cluster flips, moments).  Asynchronous on the handle's stream;
+ * records are kept on the device and drained to the host automatically when
+ * the device ring fills (which synchronises).  Errors: PYRO_EINVAL
+ * (n_sweeps < 0), PYRO_EDEVICE, PYRO_ESTATE.
+ */
+int pyro_sw_sweep(pyro_sw *h, int64_t n_sweeps);
+
+/*
+ * Synchronise and move up to cap records, oldest first, into out[0..cap-1];
+ * *n_out receives the number written.  Records not returned stay queued for
+ * the next call.  out may be NULL only when cap == 0 (then *n_out is the
+ * number queued).
+ */
+int pyro_sw_moments(pyro_sw *h, pyro_sw_record *out, int64_t cap, int64_t *n_out);
+
+/*
+ * Copy the spins to / from host memory in the exchange layout: Ising int8
+ * [N] (+1 / -1); O(n) float [n][N], component-major.  bytes must equal that
+ * size.  set_spins also sets the global index of the next sweep (random
+ * draws depend on it), and discards queued records.  Synchronising.
+ */
+int pyro_sw_get_spins(pyro_sw *h, void *host, size_t bytes);
+int pyro_sw_set_spins(pyro_sw *h, const void *host, size_t bytes, int64_t next_sweep);
+
+/*
+ * Cluster label of every site after the last sweep: the smallest site index
+ * in its cluster.  n must equal N.  Before the first sweep: label[i] = i.
+ * Synchronising.
+ */
+int pyro_sw_get_labels(pyro_sw *h, int32_t *host, size_t n);
+
+/*
+ * Change the temperature (takes effect from the next enqueued sweep).
+ * Errors: PYRO_EINVAL for T <= 0 or NaN.
+ */
+int pyro_sw_set_temperature(pyro_sw *h, double T);
+
+/* Number of sites N and global index of the next sweep. */
+int pyro_sw_info(const pyro_sw *h, int64_t *n_sites, int64_t *next_sweep);
+
+/*
+ * Kernel timing.  kernel_mask selects kernels by their index in the list
+ * pyro_sw_kernel_times returns (bit k = kernel k; -1 = all, 0 = off).  Every
+ * launch of a selected kernel is bracketed by HIP events on the handle's
+ * stream.  pyro_sw_kernel_times synchronises and returns, per kernel name,
+ * the number of timed launches and their summed duration in milliseconds
+ * since the last pyro_sw_set_timing call.  names[k] point to static strings;
+ * *n_out receives the number of kernels.
+ */
+int pyro_sw_set_timing(pyro_sw *h, int kernel_mask);
+int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, double *ms,
+                         int cap, int *n_out);
+
+/* Synchronise and free everything the library allocated.  NULL is a no-op. */
+int pyro_sw_destroy(pyro_sw *h);
+
+/* Static text for a status code. */
+const char *pyro_sw_strerror(int status);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *pyro_sw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYRO_SW_H */

@@ -1,0 +1,271 @@
+"""Python binding of the C ABI in ``include/pyro_sw.h`` (argument marshalling
+only; every step of the sweep runs in the HIP library ``libpyrosw.so``).
+
+Functions carry the C names.  ``Lattice`` is a convenience wrapper whose
+device memory (spins and workspace) is owned by PyTorch tensors and whose
+work runs on a PyTorch (HIP) stream.
+
+If the library has not been built, loading fails loudly: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpyrosw.so")
+
+PYRO_ISING, PYRO_XY, PYRO_HEISENBERG = 1, 2, 3
+PYRO_START_COLD, PYRO_START_RANDOM = 0, 1
+PYRO_OK, PYRO_EINVAL, PYRO_ENOMEM, PYRO_EDEVICE, PYRO_ESTATE = 0, -1, -2, -3, -4
+
+# Same field order and size (80 bytes) as pyro_sw_record.
+RECORD_DTYPE = np.dtype(
+    [
+        ("sweep", "<i8"),
+        ("bond_sum", "<i8"),
+        ("M_int", "<i8"),
+        ("reserved", "<i8"),
+        ("E", "<f8"),
+        ("M", "<f8", (3,)),
+        ("m2", "<f8"),
+        ("m4", "<f8"),
+    ]
+)
+
+# Every symbol the header declares.
+EXPORTS = (
+    "pyro_sw_init", "pyro_sw_workspace_size", "pyro_sw_init_ext", "pyro_sw_sweep",
+    "pyro_sw_moments", "pyro_sw_get_spins", "pyro_sw_set_spins", "pyro_sw_get_labels",
+    "pyro_sw_set_temperature", "pyro_sw_info", "pyro_sw_set_timing", "pyro_sw_kernel_times",
+    "pyro_sw_destroy", "pyro_sw_strerror", "pyro_sw_last_error",
+)
+
+
+class PyroSWError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {pyro_sw_strerror(status)} ({status}): {last_error()}")
+
+
+_lib = None
+
+
+def load_library():
+    """Load ``libpyrosw.so``; raises if it is missing (build it first with
+    ``python -m paper_1612_08312_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run python -m paper_1612_08312_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, u64, i32, f64, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_size_t)
+    P = ctypes.POINTER
+    lib.pyro_sw_init.argtypes = [P(vp), i32, i32, f64, f64, u64, i32, vp]
+    lib.pyro_sw_workspace_size.argtypes = [i32, i32, P(sz), P(sz)]
+    lib.pyro_sw_init_ext.argtypes = [P(vp), i32, i32, f64, f64, u64, i32, vp, vp, sz, vp, sz]
+    lib.pyro_sw_sweep.argtypes = [vp, i64]
+    lib.pyro_sw_moments.argtypes = [vp, vp, i64, P(i64)]
+    lib.pyro_sw_get_spins.argtypes = [vp, vp, sz]
+    lib.pyro_sw_set_spins.argtypes = [vp, vp, sz, i64]
+    lib.pyro_sw_get_labels.argtypes = [vp, vp, sz]
+    lib.pyro_sw_set_temperature.argtypes = [vp, f64]
+    lib.pyro_sw_info.argtypes = [vp, P(i64), P(i64)]
+    lib.pyro_sw_set_timing.argtypes = [vp, i32]
+    lib.pyro_sw_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
+    lib.pyro_sw_destroy.argtypes = [vp]
+    lib.pyro_sw_strerror.argtypes = [i32]
+    lib.pyro_sw_strerror.restype = ctypes.c_char_p
+    lib.pyro_sw_last_error.argtypes = []
+    lib.pyro_sw_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("pyro_sw_strerror", "pyro_sw_last_error"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def pyro_sw_strerror(status: int) -> str:
+    return load_library().pyro_sw_strerror(int(status)).decode()
+
+
+def last_error() -> str:
+    return load_library().pyro_sw_last_error().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != PYRO_OK:
+        raise PyroSWError(rc, where)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def pyro_sw_init(L, model, T, J=1.0, seed=1, start=PYRO_START_RANDOM, stream=None):
+    h = ctypes.c_void_p()
+    _check(load_library().pyro_sw_init(ctypes.byref(h), int(L), int(model), float(T), float(J),
+                                       int(seed), int(start), _stream_ptr(stream)), "pyro_sw_init")
+    return h
+
+
+def pyro_sw_workspace_size(L, model):
+    s, w = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().pyro_sw_workspace_size(int(L), int(model), ctypes.byref(s), ctypes.byref(w)),
+           "pyro_sw_workspace_size")
+    return s.value, w.value
+
+
+def pyro_sw_init_ext(L, model, T, J, seed, start, stream, dev_spins, spin_bytes, dev_work, work_bytes):
+    h = ctypes.c_void_p()
+    _check(load_library().pyro_sw_init_ext(ctypes.byref(h), int(L), int(model), float(T), float(J),
+                                           int(seed), int(start), _stream_ptr(stream), int(dev_spins),
+                                           int(spin_bytes), int(dev_work), int(work_bytes)),
+           "pyro_sw_init_ext")
+    return h
+
+
+def pyro_sw_sweep(h, n_sweeps):
+    _check(load_library().pyro_sw_sweep(h, int(n_sweeps)), "pyro_sw_sweep")
+
+
+def pyro_sw_moments(h, cap=None) -> np.ndarray:
+    lib = load_library()
+    n = ctypes.c_int64()
+    if cap is None:
+        _check(lib.pyro_sw_moments(h, None, 0, ctypes.byref(n)), "pyro_sw_moments")
+        cap = n.value
+    out = np.zeros(int(cap), dtype=RECORD_DTYPE)
+    if cap == 0:
+        return out
+    _check(lib.pyro_sw_moments(h, out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n)),
+           "pyro_sw_moments")
+    return out[: n.value]
+
+
+def pyro_sw_info(h):
+    n, t = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().pyro_sw_info(h, ctypes.byref(n), ctypes.byref(t)), "pyro_sw_info")
+    return n.value, t.value
+
+
+def pyro_sw_get_spins(h, model) -> np.ndarray:
+    N, _ = pyro_sw_info(h)
+    out = np.zeros(N, np.int8) if model == PYRO_ISING else np.zeros((model, N), np.float32)
+    _check(load_library().pyro_sw_get_spins(h, out.ctypes.data_as(ctypes.c_void_p), out.nbytes),
+           "pyro_sw_get_spins")
+    return out
+
+
+def pyro_sw_set_spins(h, spins: np.ndarray, next_sweep: int):
+    a = np.ascontiguousarray(spins)
+    _check(load_library().pyro_sw_set_spins(h, a.ctypes.data_as(ctypes.c_void_p), a.nbytes, int(next_sweep)),
+           "pyro_sw_set_spins")
+
+
+def pyro_sw_get_labels(h) -> np.ndarray:
+    N, _ = pyro_sw_info(h)
+    out = np.zeros(N, np.int32)
+    _check(load_library().pyro_sw_get_labels(h, out.ctypes.data_as(ctypes.c_void_p), N), "pyro_sw_get_labels")
+    return out
+
+
+def pyro_sw_set_temperature(h, T):
+    _check(load_library().pyro_sw_set_temperature(h, float(T)), "pyro_sw_set_temperature")
+
+
+def pyro_sw_set_timing(h, kernel_mask: int = -1):
+    """Bracket launches of the selected kernels with HIP events (bit k =
+    kernel k of pyro_sw_kernel_times; -1 all; 0 off)."""
+    _check(load_library().pyro_sw_set_timing(h, int(kernel_mask)), "pyro_sw_set_timing")
+
+
+def pyro_sw_kernel_times(h) -> dict:
+    cap = 32
+    names = (ctypes.c_char_p * cap)()
+    launches = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = ctypes.c_int()
+    _check(load_library().pyro_sw_kernel_times(h, names, launches, ms, cap, ctypes.byref(n)),
+           "pyro_sw_kernel_times")
+    return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(n.value)}
+
+
+def pyro_sw_destroy(h):
+    if h is not None and h.value:
+        _check(load_library().pyro_sw_destroy(h), "pyro_sw_destroy")
+        h.value = None
+
+
+class Lattice:
+    """One simulated lattice whose device memory belongs to PyTorch tensors.
+
+    The library enqueues all work on ``stream`` (default: PyTorch's current
+    stream of ``device``)."""
+
+    def __init__(self, L, model, T, J=1.0, seed=1, start=PYRO_START_RANDOM, device="cuda:0", stream=None):
+        import torch
+
+        load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.L, self.model, self.T, self.J, self.seed, self.start = L, model, T, J, seed, start
+        sb, wb = pyro_sw_workspace_size(L, model)
+        with torch.cuda.device(self.device):
+            self.spin_mem = torch.empty(sb, dtype=torch.uint8, device=self.device)
+            self.work_mem = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.h = pyro_sw_init_ext(L, model, T, J, seed, start, self.stream, self.spin_mem.data_ptr(), sb,
+                                  self.work_mem.data_ptr(), wb)
+        self.N = 16 * L ** 3
+
+    def sweep(self, n=1):
+        pyro_sw_sweep(self.h, n)
+
+    def moments(self, cap=None) -> np.ndarray:
+        return pyro_sw_moments(self.h, cap)
+
+    def spins(self) -> np.ndarray:
+        return pyro_sw_get_spins(self.h, self.model)
+
+    def set_spins(self, s, next_sweep):
+        pyro_sw_set_spins(self.h, s, next_sweep)
+
+    def labels(self) -> np.ndarray:
+        return pyro_sw_get_labels(self.h)
+
+    def set_temperature(self, T):
+        self.T = T
+        pyro_sw_set_temperature(self.h, T)
+
+    @property
+    def next_sweep(self) -> int:
+        return pyro_sw_info(self.h)[1]
+
+    def spins_tensor(self):
+        """Device view of the spins (int8 [N] or float32 [n, N])."""
+        import torch
+
+        if self.model == PYRO_ISING:
+            return self.spin_mem[: self.N].view(torch.int8)
+        return self.spin_mem[: 4 * self.model * self.N].view(torch.float32).view(self.model, self.N)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            pyro_sw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

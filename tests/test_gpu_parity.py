@@ -1,0 +1,186 @@
+"""Parity of the HIP sweep (through the C ABI) with the CPU oracle.
+
+Ising: per-sweep records (exact integer bond sum and magnetisation, and the
+doubles derived from them), spins and cluster labels are compared bit for
+bit.  O(n): spins and labels are expected bit-identical (same FP32 operation
+order on both sides, explicit fused multiply-adds, no contraction); records
+are compared within 1e-5 relative (FP64 sums in a different order).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_08312_amd import pyrosw, workloads
+
+pytestmark = pytest.mark.gpu
+
+REC_INT = ("sweep", "bond_sum", "M_int")
+REC_FLT = ("E", "m2", "m4")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_lattice(**kw):
+    say("GPU case:", kw)
+    return pyrosw.Lattice(**kw)
+
+
+def assert_records_exact(g, o):
+    assert len(g) == len(o)
+    for f in REC_INT:
+        np.testing.assert_array_equal(g[f], o[f], err_msg=f)
+    for f in REC_FLT:
+        np.testing.assert_array_equal(g[f], o[f], err_msg=f)
+    np.testing.assert_array_equal(g["M"], o["M"])
+
+
+def assert_records_close(g, o, rtol=1e-5):
+    assert len(g) == len(o)
+    np.testing.assert_array_equal(g["sweep"], o["sweep"])
+    np.testing.assert_allclose(g["E"], o["E"], rtol=rtol, atol=1e-9)
+    np.testing.assert_allclose(g["M"], o["M"], rtol=rtol, atol=1e-6 * np.sqrt(np.abs(o["M"]).max() + 1))
+    np.testing.assert_allclose(g["m2"], o["m2"], rtol=rtol, atol=1e-12)
+    np.testing.assert_allclose(g["m4"], o["m4"], rtol=rtol, atol=1e-12)
+
+
+def run_both(L, model, T, seed, start, sweeps, chunks=1, J=1.0):
+    g = gpu_lattice(L=L, model=model, T=T, J=J, seed=seed, start=start)
+    o = oracle.Oracle(L=L, model=model, T=T, J=J, seed=seed, start=start)
+    if model == 1:
+        np.testing.assert_array_equal(g.spins(), o.spins())
+    else:
+        np.testing.assert_array_equal(g.spins(), o.spins())
+    per = sweeps // chunks
+    grec, orec = [], []
+    for _ in range(chunks):
+        g.sweep(per)
+        grec.append(g.moments())
+        orec.append(o.sweep(per))
+    return g, o, np.concatenate(grec), np.concatenate(orec)
+
+
+def test_small_ising_full_trajectory_bit_exact():
+    c = workloads.SMALL_ISING
+    g, o, gr, orr = run_both(c["L"], c["model"], c["T"], c["seed"], c["start"], c["sweeps"], chunks=4)
+    assert_records_exact(gr, orr)
+    np.testing.assert_array_equal(g.spins(), o.spins())
+    np.testing.assert_array_equal(g.labels(), o.labels())
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 7])
+def test_ising_small_and_ragged_lattices(L):
+    g, o, gr, orr = run_both(L, 1, 4.2139, 100 + L, workloads.RANDOM, 200, chunks=2)
+    assert_records_exact(gr, orr)
+    np.testing.assert_array_equal(g.spins(), o.spins())
+    np.testing.assert_array_equal(g.labels(), o.labels())
+
+
+@pytest.mark.parametrize("T", [0.5, 3.0, 4.2139, 6.0, 50.0])
+def test_ising_temperatures(T):
+    g, o, gr, orr = run_both(6, 1, T, 7, workloads.RANDOM, 30)
+    assert_records_exact(gr, orr)
+    np.testing.assert_array_equal(g.labels(), o.labels())
+
+
+def test_ising_infinite_and_zero_temperature():
+    g, o, gr, orr = run_both(4, 1, float("inf"), 3, workloads.RANDOM, 20)
+    assert_records_exact(gr, orr)
+    np.testing.assert_array_equal(g.labels(), np.arange(g.N))
+    g, o, gr, orr = run_both(4, 1, 1e-3, 3, workloads.COLD, 20)
+    assert_records_exact(gr, orr)
+    assert np.all(g.labels() == 0)
+    assert np.all(gr["m2"] == 1.0)
+
+
+def test_ising_resume_and_set_spins():
+    """S sweeps == S1 sweeps, copy the state out and back in, S - S1 sweeps."""
+    g = gpu_lattice(L=4, model=1, T=4.2139, seed=9, start=1)
+    g.sweep(50)
+    ref = g.moments()
+    s_end = g.spins()
+    h = gpu_lattice(L=4, model=1, T=4.2139, seed=9, start=1)
+    h.sweep(20)
+    first = h.moments()
+    mid = h.spins()
+    k = gpu_lattice(L=4, model=1, T=4.2139, seed=9, start=0)
+    k.set_spins(mid, 20)
+    k.sweep(30)
+    rest = k.moments()
+    assert_records_exact(np.concatenate([first, rest]), ref)
+    np.testing.assert_array_equal(k.spins(), s_end)
+
+
+def test_ising_from_seeded_configuration():
+    N = workloads.n_sites(3)
+    s0 = workloads.random_ising_spins(N, 4)
+    g = gpu_lattice(L=3, model=1, T=4.0, seed=5, start=0)
+    o = oracle.Oracle(L=3, model=1, T=4.0, seed=5, start=0)
+    g.set_spins(s0, 1234)
+    o.set_spins(s0, 1234)
+    g.sweep(25)
+    assert_records_exact(g.moments(), o.sweep(25))
+    np.testing.assert_array_equal(g.labels(), o.labels())
+
+
+def test_ising_l128_first_sweeps_bit_exact():
+    """Full-size lattice (33,554,432 sites): the first three sweeps from the
+    random start, at the centre temperature of the five-temperature run."""
+    c = workloads.ISING_L128
+    T, seed = c["temps"][2], c["seeds"][2]
+    g = gpu_lattice(L=128, model=1, T=T, seed=seed, start=c["start"])
+    o = oracle.Oracle(L=128, model=1, T=T, seed=seed, start=c["start"])
+    np.testing.assert_array_equal(g.spins(), o.spins())
+    for _ in range(3):
+        g.sweep(1)
+        assert_records_exact(g.moments(), o.sweep(1))
+        np.testing.assert_array_equal(g.labels(), o.labels())
+        np.testing.assert_array_equal(g.spins(), o.spins())
+        say("L=128 sweep ok")
+
+
+@pytest.mark.parametrize("model,L,T", [(2, 3, 2.0285), (3, 3, 1.31695), (2, 8, 2.0285), (3, 8, 1.31695),
+                                       (2, 5, 0.8), (3, 4, 3.0)])
+def test_on_parity(model, L, T):
+    g, o, gr, orr = run_both(L, model, T, 1, workloads.RANDOM, 20, chunks=2)
+    assert_records_close(gr, orr)
+    np.testing.assert_array_equal(g.labels(), o.labels())
+    np.testing.assert_allclose(g.spins(), o.spins(), rtol=0, atol=1e-5)
+
+
+def test_on_cold_start_and_infinite_temperature():
+    g, o, gr, orr = run_both(3, 3, float("inf"), 2, workloads.COLD, 10)
+    assert_records_close(gr, orr)
+    np.testing.assert_array_equal(g.labels(), np.arange(g.N))
+
+
+def test_on_l64_first_sweeps():
+    """Full-size O(n) lattices (4,194,304 sites): first sweeps within 1e-5."""
+    for c in workloads.ON_L64:
+        g = gpu_lattice(L=c["L"], model=c["model"], T=c["T"], seed=c["seed"], start=c["start"])
+        o = oracle.Oracle(L=c["L"], model=c["model"], T=c["T"], seed=c["seed"], start=c["start"])
+        g.sweep(3)
+        assert_records_close(g.moments(), o.sweep(3))
+        np.testing.assert_array_equal(g.labels(), o.labels())
+        np.testing.assert_allclose(g.spins(), o.spins(), rtol=0, atol=1e-5)
+
+
+def test_determinism_repeat():
+    a = gpu_lattice(L=8, model=1, T=4.2139, seed=77, start=1)
+    b = gpu_lattice(L=8, model=1, T=4.2139, seed=77, start=1)
+    a.sweep(40)
+    b.sweep(40)
+    assert_records_exact(a.moments(), b.moments())
+    np.testing.assert_array_equal(a.labels(), b.labels())
+
+
+def test_timing_counters():
+    g = gpu_lattice(L=8, model=1, T=4.2139, seed=1, start=1)
+    pyrosw.pyro_sw_set_timing(g.h, True)
+    g.sweep(5)
+    t = pyrosw.pyro_sw_kernel_times(g.h)
+    assert sum(v[0] for v in t.values()) > 0
+    assert all(v[1] >= 0 for v in t.values())
