@@ -64,10 +64,10 @@ __device__ void unit_vector(uint32_t c0, uint32_t c1, uint32_t stream, int n, Ph
         r2 = __fmaf_rn(v1, v1, r2);
         if (n == 3) r2 = __fmaf_rn(v2, v2, r2);
         if (r2 > 1e-12f && r2 <= 1.0f) {
-            const float nr = __fsqrt_rn(r2);
-            out[0] = __fdiv_rn(v0, nr);
-            out[1] = __fdiv_rn(v1, nr);
-            out[2] = n == 3 ? __fdiv_rn(v2, nr) : 0.0f;
+            const float nr = sqrtf(r2);
+            out[0] = v0 / nr;
+            out[1] = v1 / nr;
+            out[2] = n == 3 ? v2 / nr : 0.0f;
             return;
         }
     }

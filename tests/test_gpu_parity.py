@@ -179,7 +179,7 @@ def test_determinism_repeat():
 
 def test_timing_counters():
     g = gpu_lattice(L=8, model=1, T=4.2139, seed=1, start=1)
-    pyrosw.pyro_sw_set_timing(g.h, True)
+    pyrosw.pyro_sw_set_timing(g.h, -1)
     g.sweep(5)
     t = pyrosw.pyro_sw_kernel_times(g.h)
     assert sum(v[0] for v in t.values()) > 0
