@@ -27,17 +27,22 @@ sys.path.insert(0, ROOT)
 METRIC = "SW spin-updates/sec and % HBM roofline, Ising L=128; batched vs plain, p99 job latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
-# Algorithmic HBM bytes per site of one launch of each Ising kernel (each
-# array element read or written once; halo re-reads and L2/MALL hits not
-# counted).  Per-cell arrays are spread over the cell's 16 sites.
+# Algorithmic HBM bytes per site of one launch of each Ising kernel: every
+# array element the kernel must touch, read or written once (halo re-reads,
+# root look-ups and L2/MALL hits not counted).  Tiles are 8x8x4 cells; 109 of
+# their 256 cells lie on a low face and store an 8-byte mask of the active
+# bonds that leave the tile.
+FACE_MASK_BYTES = 8.0 * 109 / 256 / 16
 BYTES_PER_SITE = {
-    "bonds": 1.0 + 4.0 + 8.0 / 16,    # read spins, write identity labels, write 48-bit masks
-    "union": 8.0 / 16 + 4.0,          # read masks, touch labels of bond ends
-    "flip_table": 1.0 / 8,            # write one flip bit per site
-    "flip": 4.0 + 4.0 + 1.0 + 1.0,    # read/write labels, read/write spins
-    "energy": 1.0,                    # read spins
+    "local": 1.0 + 4.0 + FACE_MASK_BYTES,  # read spins, write tile-local roots, face masks
+    "merge": FACE_MASK_BYTES,              # read face masks (label traffic is data dependent)
+    "compress": FACE_MASK_BYTES,           # read face masks
+    "coins": 1.0 / 8,                      # write one flip coin per site
+    "flip": 4.0 + 1.0 + 1.0,               # read labels, read and write spins
+    "energy": 1.0,                         # read spins
     "finalize": 0.0,
 }
+SWEEP_BYTES_PER_SITE = 11.0  # whole-sweep model: read s, write/read labels, read/write s
 
 
 def log(*a):
@@ -65,6 +70,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for cpu_baseline (0: skip)")
+    ap.add_argument("--tile-shape", type=int, default=-1, help="tile shape id (-1: autotune)")
+    ap.add_argument("--roofline-steps", type=int, default=200,
+                    help="steps of the pass that times the dominant kernel with HIP events")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -87,52 +95,49 @@ def main():
     lats = [pyrosw.Lattice(L=L, model=1, T=T, seed=s, start=cfg["start"], device=dev, stream=stream)
             for T, s in zip(temps, seeds)]
     N = lats[0].N
+    group = pyrosw.Group(lats, stream)
+    if args.tile_shape >= 0:
+        group.set_tile_shape(1, args.tile_shape)
+    else:
+        shapes = group.autotune(trial_sweeps=3)
+        log("bench: autotuned tile shape", pyrosw.TILE_SHAPES[shapes[0]])
 
-    # Find the dominant kernel over a few timed sweeps.
-    for lt in lats:
-        pyrosw.pyro_sw_set_timing(lt.h, -1)
-    for _ in range(max(1, min(args.warmup, 5))):
-        for lt in lats:
-            lt.sweep(1)
-    kt = {}
-    for lt in lats:
-        for k, (n, ms) in pyrosw.pyro_sw_kernel_times(lt.h).items():
-            a = kt.setdefault(k, [0, 0.0])
-            a[0] += n
-            a[1] += ms
+    # Find the dominant kernel over a few timed sweeps (events on every kernel).
+    pyrosw.pyro_sw_group_set_timing(group.g, -1)
+    group.sweep(max(1, min(args.warmup, 5)))
+    kt = {k: list(v) for k, v in pyrosw.pyro_sw_group_kernel_times(group.g).items()}
     names = list(kt)
     dominant = max(kt, key=lambda k: kt[k][1])
-    log("bench: kernel shares over probe sweeps:",
-        {k: round(v[1] / max(v[0], 1), 4) for k, v in kt.items() if v[0]})
+    log("bench: mean us per launch over probe sweeps:",
+        {k: round(v[1] / v[0] * 1e3, 1) for k, v in kt.items() if v[0]})
 
     # Warmup, then the timed region with HIP events on the dominant kernel only.
-    for _ in range(args.warmup):
-        for lt in lats:
-            lt.sweep(1)
+    pyrosw.pyro_sw_group_set_timing(group.g, 0)
+    group.sweep(args.warmup)
     for lt in lats:
         lt.moments()  # discard warmup records
-        pyrosw.pyro_sw_set_timing(lt.h, 1 << names.index(dominant))
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for lt in lats:
-            lt.sweep(1)
+    group.sweep(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    dom_n, dom_ms = 0, 0.0
-    for lt in lats:
-        n, ms = pyrosw.pyro_sw_kernel_times(lt.h)[dominant]
-        dom_n += n
-        dom_ms += ms
     recs = [lt.moments() for lt in lats]
+    # Mean duration of the dominant kernel: HIP events around each of its
+    # launches on the group's stream (direct launches instead of the graph).
+    roof_steps = max(1, min(args.steps, args.roofline_steps))
+    pyrosw.pyro_sw_group_set_timing(group.g, 1 << names.index(dominant))
+    group.sweep(roof_steps)
+    dom_n, dom_ms = pyrosw.pyro_sw_group_kernel_times(group.g)[dominant]
+    group.close()
     for lt in lats:
         lt.close()
 
     updates = N * len(lats) * args.steps
     value = updates / dt
     dom_avg_s = dom_ms / max(dom_n, 1) / 1e3
-    bytes_per_launch = BYTES_PER_SITE.get(dominant, 0.0) * N
+    # one launch of a kernel covers all lattices of the group
+    bytes_per_launch = BYTES_PER_SITE.get(dominant, 0.0) * N * len(lats)
     achieved = bytes_per_launch / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
     binder = {}
     for T, r in zip(temps, recs):
@@ -161,7 +166,7 @@ def main():
             "seeds": list(seeds),
             "start": "random",
             "sweeps_per_lattice": args.steps,
-            "step": "one SW sweep of each lattice",
+            "step": "one SW sweep of each lattice (one captured graph for all five)",
         },
         "roofline": {
             "bound": "hbm",
@@ -173,10 +178,11 @@ def main():
             "traffic": None,
             "alg_bytes_per_site": BYTES_PER_SITE.get(dominant, 0.0),
             "mean_launch_us": dom_avg_s * 1e6,
+            "timed_launches": dom_n,
         },
-        "sweep_alg_roofline_frac": value * 11.0 / (HBM_PEAK_GBS * 1e9),
+        "sweep_alg_roofline_frac": value * SWEEP_BYTES_PER_SITE / (HBM_PEAK_GBS * 1e9),
         "binder_U_second_half": binder,
-        "kernel_mean_us": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},
+        "kernel_mean_us_probe": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},
     }
     if args.cpu_sweeps > 0:
         log("bench: timing the CPU oracle")

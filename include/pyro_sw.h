@@ -111,10 +111,11 @@ int pyro_sw_init_ext(pyro_sw **out, int L, int model, double T, double J, uint64
 
 /*
  * Enqueue n_sweeps >= 0 Swendsen-Wang sweeps (bond activation, cluster
- * labeling, cluster flips, moments).  Asynchronous on the handle's stream;
- * records are kept on the device and drained to the host automatically when
- * the device ring fills (which synchronises).  Errors: PYRO_EINVAL
- * (n_sweeps < 0), PYRO_EDEVICE, PYRO_ESTATE.
+ * labeling, cluster flips, moments).  Asynchronous on the handle's stream
+ * (one captured graph replayed per sweep); records are kept on the device and
+ * drained to the host automatically when the device ring of 16384 records
+ * fills (which synchronises).  Errors: PYRO_EINVAL (n_sweeps < 0),
+ * PYRO_EDEVICE, PYRO_ESTATE.
  */
 int pyro_sw_sweep(pyro_sw *h, int64_t n_sweeps);
 
@@ -148,6 +149,15 @@ int pyro_sw_get_labels(pyro_sw *h, int32_t *host, size_t n);
  */
 int pyro_sw_set_temperature(pyro_sw *h, double T);
 
+/*
+ * Tile shape of the cluster labeling: the lattice is cut into boxes of cells,
+ * each labelled in one workgroup's local memory before the boxes are merged.
+ * The shape changes speed only, never results (labels are canonical and all
+ * draws are keyed by sweep and site or bond).
+ */
+enum { PYRO_TILE_8x8x4 = 0, PYRO_TILE_8x4x4 = 1, PYRO_TILE_4x4x4 = 2, PYRO_TILE_8x8x8 = 3 };
+int pyro_sw_set_tile_shape(pyro_sw *h, int shape);
+
 /* Number of sites N and global index of the next sweep. */
 int pyro_sw_info(const pyro_sw *h, int64_t *n_sites, int64_t *next_sweep);
 
@@ -163,6 +173,44 @@ int pyro_sw_info(const pyro_sw *h, int64_t *n_sites, int64_t *next_sweep);
 int pyro_sw_set_timing(pyro_sw *h, int kernel_mask);
 int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, double *ms,
                          int cap, int *n_out);
+
+/*
+ * Groups: many lattices (any mix of L, model, T, seed) swept together.  Each
+ * sweep of a group is one captured HIP graph whose kernels cover every
+ * member (one launch per step of the sweep for all lattices of a model),
+ * replayed once per sweep on the group's stream.  Every member's trajectory
+ * is bit-identical to sweeping it alone.
+ *   pyro_sw_group_create   members stay owned by the caller and must outlive
+ *                          the group; stream as in pyro_sw_init.  A lattice
+ *                          may belong to several groups but must not be used
+ *                          by two calls at once.
+ *   pyro_sw_group_sweep    n_sweeps sweeps of every member, or, when
+ *                          per_member is not NULL, per_member[i] sweeps of
+ *                          member i (members with fewer sweeps idle while the
+ *                          others run).  Records go to each member, read with
+ *                          pyro_sw_moments on the member.
+ *   pyro_sw_group_autotune times trial_sweeps (1..1000) sweeps of each model
+ *                          with every tile shape, keeps the fastest per model
+ *                          (also for later groups of the same lattice sizes
+ *                          in this process), and restores every member's
+ *                          spins, sweep index and records, so tuning changes
+ *                          no result.  shapes_out[3] (may be NULL) receives
+ *                          the shapes for Ising, XY, Heisenberg.
+ *   pyro_sw_group_set_tile_shape  fix the shape of one model's lattices.
+ *   pyro_sw_group_set_timing / pyro_sw_group_kernel_times  as for a handle.
+ *   pyro_sw_group_destroy  frees the group only (NULL is a no-op).
+ * Errors: PYRO_EINVAL (arguments), PYRO_ESTATE (a member failed or is busy),
+ * PYRO_ENOMEM, PYRO_EDEVICE.
+ */
+typedef struct pyro_sw_group pyro_sw_group;
+int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, void *stream);
+int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_member);
+int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out);
+int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape);
+int pyro_sw_group_set_timing(pyro_sw_group *g, int kernel_mask);
+int pyro_sw_group_kernel_times(pyro_sw_group *g, const char **names, int64_t *launches, double *ms,
+                               int cap, int *n_out);
+int pyro_sw_group_destroy(pyro_sw_group *g);
 
 /* Synchronise and free everything the library allocated.  NULL is a no-op. */
 int pyro_sw_destroy(pyro_sw *h);

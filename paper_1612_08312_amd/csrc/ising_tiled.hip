@@ -1,0 +1,293 @@
+// Ising Swendsen-Wang sweep on gfx950 with LDS-tiled cluster labeling, for a
+// chain of lattices (kernels.hpp).
+//
+// One sweep (method of Sec. 1-2 of the paper; random draws as documented in
+// ising_cell.hpp):
+//   k_local_ising  one workgroup per tile: stage the 16-bit spin masks of the
+//                  tile in LDS, activate the 48 bonds of every cell, merge
+//                  each up tetrahedron with a K4 component table, unite the
+//                  down-tetrahedron bonds inside the tile in an LDS forest,
+//                  write every site's tile-local root as a global site index
+//                  and record the active bonds that leave the tile.  The
+//                  parallel-bond count is the energy of the incoming state.
+//   k_merge / k_compress_roots  the tile-crossing bonds (tile_common.hpp).
+//   k_coins        flip coins (tile_common.hip).
+//   k_flip_ising   per cell: roots of its 16 sites, flip coins, XOR flip of
+//                  the int8 spins, magnetisation of the new state.
+//   k_finalize_ising  fixed-order sums of the partials into the records,
+//                  then advance the replica's state.
+// Local site order inside a tile follows the global order, so every root is
+// the smallest site index of its cluster whatever the schedule.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_util.hpp"
+#include "ising_cell.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "philox.hpp"
+#include "tile_common.hpp"
+
+namespace pyro {
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
+{
+    constexpr int NC = TX * TY * TZ;
+    constexpr int NS = 16 * NC;
+    __shared__ int P[NS];
+    __shared__ uint32_t SM[NC];
+    __shared__ uint8_t K4[64];
+    __shared__ int64_t red[16];
+
+    const int rep = c.tile_rep[blockIdx.x];
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int tile = blockIdx.x - d.tile_base;
+    const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
+    const int8_t *__restrict__ s = (const int8_t *)d.spins;
+    const int tid = threadIdx.x;
+    const int L = d.L;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
+    const bool valid = x < L && y < L && z < L;
+    const int cell = (z * L + y) * L + x;
+
+    if (tid < 64) {
+        constexpr K4Table k4 = make_k4();
+        K4[tid] = k4.v[tid];
+    }
+    uint32_t m = 0;
+    if (valid) m = spin_mask16(reinterpret_cast<const int4 *>(s)[cell]);
+    SM[tid] = m;
+    __syncthreads();
+
+    uint64_t act = 0;
+    int aligned_count = 0;
+    NbrCell nb[kNCellCodes];
+    if (valid) {
+        ti.neighbours(x, y, z, cell, tid, nb);
+        uint32_t nm[kNCellCodes];
+        nm[kSelf] = m;
+#pragma unroll
+        for (int q = 1; q < kNCellCodes; ++q)
+            nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell]
+                                     : spin_mask16(reinterpret_cast<const int4 *>(s)[nb[q].gcell]);
+        const uint32_t dm = down_mask16(m, nm[kMx], nm[kMy], nm[kMz], nm[kMyMz], nm[kMxMz], nm[kMxMy]);
+        const uint64_t al = aligned48(m, dm);
+        aligned_count = (int)__popcll(al);
+        act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
+    }
+    // Up tetrahedra: components from the table, roots at the smallest vertex.
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
+        const int base = 16 * tid + 4 * f;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
+    }
+    __syncthreads();
+    // Down tetrahedra: unite inside the tile, record the bonds that leave it.
+    if (valid) {
+        uint64_t xm_bits = 0;
+        const uint32_t down = (uint32_t)(act >> 24);
+#pragma unroll
+        for (int jj = 0; jj < 24; ++jj) {
+            if (!((down >> jj) & 1u)) continue;
+            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
+            const int la = nb[A.cell].lcell, lb = nb[B.cell].lcell;
+            if (la >= 0 && lb >= 0)
+                lds_unite<NC>(P, 16 * la + A.site, 16 * lb + B.site);
+            else
+                xm_bits |= 1ull << (24 + jj);
+        }
+        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = xm_bits;
+    }
+    __syncthreads();
+    if (valid) {
+        int r[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) r[k] = ti.global_site(lds_find<NC>(P, 16 * tid + k));
+        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+    }
+    const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - 48) : 0, red);
+    if (tid == 0) d.ipart[tile] = bsum;
+}
+
+// One thread per cell: roots of its 16 sites, flips, and the magnetisation
+// of the new state.
+__global__ __launch_bounds__(kBlock) void k_flip_ising(Chain c)
+{
+    __shared__ int64_t red[16];
+    const int rep = c.cblk_rep[blockIdx.x];
+    if (c.state[rep]->remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int blk = blockIdx.x - d.cblk_base;
+    const int64_t cl = (int64_t)blk * kBlock + threadIdx.x;
+    const int32_t *__restrict__ label = d.label;
+    const uint32_t *__restrict__ fb = d.coins;
+    int mag = 0;
+    if (cl < d.ncell) {
+        const int4 *L4 = reinterpret_cast<const int4 *>(label + 16 * cl);
+        int lab[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 v = L4[q];
+            lab[4 * q] = v.x;
+            lab[4 * q + 1] = v.y;
+            lab[4 * q + 2] = v.z;
+            lab[4 * q + 3] = v.w;
+        }
+        int4 *S4 = reinterpret_cast<int4 *>(d.spins);
+        const int4 sv = S4[cl];
+        uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
+        int last_in = -1, last_root = -1;
+        uint32_t flipmask = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int r = lab[k];
+            if (r != last_in) {
+                last_in = r;
+                r = uf_find(label, r);
+                last_root = r;
+            } else {
+                r = last_root;
+            }
+            flipmask |= ((fb[r >> 5] >> (r & 31)) & 1u) << k;
+        }
+        int down = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t f4 = (flipmask >> (4 * q)) & 15u;
+            // +1 (0x01) <-> -1 (0xFF) is XOR 0xFE on the flipped bytes
+            const uint32_t x = ((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
+                               ((f4 >> 3 & 1u) * 0xFE000000u);
+            w[q] ^= x;
+            down += (int)__popc(w[q] & 0x80808080u);
+        }
+        S4[cl] = make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
+        mag = 16 - 2 * down;
+    }
+    const int64_t msum = block_sum<int64_t>((int64_t)mag, red);
+    if (threadIdx.x == 0) d.ipart[d.mpart_off + blk] = msum;
+}
+
+// Records and state: energy partials (state before this sweep) into the
+// pending record, magnetisation of the new state into a new record.
+__global__ __launch_bounds__(kBlock) void k_finalize_ising(Chain c)
+{
+    __shared__ int64_t red[16];
+    const int rep = blockIdx.x;
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int ntiles = d.ntx * d.nty * d.ntz;
+    const int ncb = blocks_for(d.ncell);
+    int64_t E = 0, M = 0;
+    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) E += d.ipart[k];
+    for (int k = threadIdx.x; k < ncb; k += blockDim.x) M += d.ipart[d.mpart_off + k];
+    E = block_sum<int64_t>(E, red);
+    M = block_sum<int64_t>(M, red);
+    if (threadIdx.x == 0) {
+        if (st.e_pending >= 0) {
+            d.ring[st.e_pending].bond_sum = E;
+            d.ring[st.e_pending].E = -d.J * (double)E;
+        }
+        const int slot = st.ring_used;
+        if (slot < d.ring_cap) {
+            DevRecord r;
+            r.sweep = st.t;
+            r.bond_sum = 0;
+            r.M_int = M;
+            r.reserved = 0;
+            r.E = 0.0;
+            r.M[0] = (double)M;
+            r.M[1] = 0.0;
+            r.M[2] = 0.0;
+            const double mm = (double)M / (double)d.N;
+            r.m2 = mm * mm;
+            r.m4 = r.m2 * r.m2;
+            d.ring[slot] = r;
+        }
+        RepState ns;
+        ns.t = st.t + 1;
+        ns.remaining = st.remaining - 1;
+        ns.ring_used = slot + 1;
+        ns.e_pending = slot < d.ring_cap ? slot : -1;
+        *c.state[rep] = ns;
+    }
+}
+
+// Energy of the current state for replicas whose last record is pending.
+__global__ __launch_bounds__(kBlock) void k_energy_ising(Chain c)
+{
+    __shared__ int64_t red[16];
+    const int rep = c.cblk_rep[blockIdx.x];
+    if (c.state[rep]->e_pending < 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int blk = blockIdx.x - d.cblk_base;
+    const int64_t cl = (int64_t)blk * kBlock + threadIdx.x;
+    int64_t B = 0;
+    if (cl < d.ncell) {
+        const int cell = (int)cl;
+        const CellNbrs nb = cell_neighbours(cell, d.L);
+        const int4 *S4 = reinterpret_cast<const int4 *>(d.spins);
+        const uint32_t m = spin_mask16(S4[cell]);
+        const uint32_t dm = down_mask16(m, spin_mask16(S4[nb.c[kMx]]), spin_mask16(S4[nb.c[kMy]]),
+                                        spin_mask16(S4[nb.c[kMz]]), spin_mask16(S4[nb.c[kMyMz]]),
+                                        spin_mask16(S4[nb.c[kMxMz]]), spin_mask16(S4[nb.c[kMxMy]]));
+        B = 2 * (int64_t)__popcll(aligned48(m, dm)) - 48;
+    }
+    const int64_t bsum = block_sum<int64_t>(B, red);
+    if (threadIdx.x == 0) d.ipart[d.mpart_off + blk] = bsum;
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_tail_finalize_ising(Chain c)
+{
+    __shared__ int64_t red[16];
+    const int rep = blockIdx.x;
+    const RepState st = *c.state[rep];
+    if (st.e_pending < 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int ncb = blocks_for(d.ncell);
+    int64_t E = 0;
+    for (int k = threadIdx.x; k < ncb; k += blockDim.x) E += d.ipart[d.mpart_off + k];
+    E = block_sum<int64_t>(E, red);
+    if (threadIdx.x == 0) {
+        d.ring[st.e_pending].bond_sum = E;
+        d.ring[st.e_pending].E = -d.J * (double)E;
+        c.state[rep]->e_pending = -1;
+    }
+}
+
+struct IsingLocal {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
+    {
+        PYRO_LAUNCH(kKLocal, (k_local_ising<TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        return hipSuccess;
+    }
+};
+
+hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    hipError_t e = with_tile_shape<IsingLocal>(c.shape, c, st, hook);
+    if (e == hipSuccess) e = launch_merge(c, st, hook);
+    if (e == hipSuccess) e = launch_coins(c, st, hook);
+    if (e != hipSuccess) return e;
+    PYRO_LAUNCH(kKFlip, k_flip_ising, c.ncell_blocks, kBlock, c);
+    PYRO_LAUNCH(kKFinalize, k_finalize_ising, c.nreps, kBlock, c);
+    return hipSuccess;
+}
+
+hipError_t launch_ising_energy_tail(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    PYRO_LAUNCH(kKEnergy, k_energy_ising, c.ncell_blocks, kBlock, c);
+    PYRO_LAUNCH(kKFinalize, k_energy_tail_finalize_ising, c.nreps, kBlock, c);
+    return hipSuccess;
+}
+
+}  // namespace pyro

@@ -1,5 +1,13 @@
-// Host-side launchers of the sweep kernels (one translation unit per model
-// family; the C-ABI layer calls only these).
+// Device-side description of the lattices a launch works on, and the
+// host-side launchers of the sweep kernels.
+//
+// Every sweep kernel handles a *chain*: a set of lattices (replicas) of one
+// model.  Each replica has a descriptor (geometry, device buffers, constants
+// of its run) and a small mutable state (sweep index, sweeps still to run,
+// record ring position) that lives in device memory, so that one captured
+// graph can replay sweeps for any set of replicas: the kernels read the
+// sweep index and skip replicas with nothing left to run, and the last
+// kernel of a sweep advances the state.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,62 +23,112 @@ struct DevRecord {
     double E, M[3], m2, m4;
 };
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;  // threads of the per-cell and per-call kernels
 
-inline int blocks_for(int64_t n, int per_block = kBlock)
+__host__ __device__ inline int blocks_for(int64_t n, int per_block = kBlock) { return (int)((n + per_block - 1) / per_block); }
+
+// Tile shapes (cells per tile edge) the library is built for.
+enum TileShape : int { kTile884 = 0, kTile844 = 1, kTile444 = 2, kTile888 = 3, kNumTileShapes };
+struct TileDims {
+    int x, y, z;
+};
+inline TileDims tile_dims(int shape)
 {
-    return (int)((n + per_block - 1) / per_block);
+    static const TileDims d[kNumTileShapes] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {8, 8, 8}};
+    return d[shape];
 }
 
-struct SweepBuffers {
-    int L;
+struct RepDesc {
+    // geometry
+    int L, ntx, nty, ntz;  // tiles per axis for the chain's tile shape
     int64_t ncell, N;
-    void *spins;          // int8 [N] or float [n][N]
-    int32_t *label;       // [N]
-    uint64_t *mask;       // [ncell] 48 activation bits per cell
-    uint32_t *flipbits;   // [4 * ceil(N/128)]
-    float *sigma;         // [N] (O(n))
-    float *axis;          // [4] (O(n))
-    int64_t *ipart;       // integer partial sums
-    double *dpart;        // floating partial sums
-    DevRecord *ring;      // per-sweep records
+    // device buffers owned by the replica
+    void *spins;       // int8 [N] or float [n][N]
+    int32_t *label;    // [N]
+    uint64_t *xmask;   // [ncell] crossing active bonds of face cells
+    uint32_t *coins;   // [4 ceil(N/128)] flip coins of the current sweep
+    int64_t *ipart;    // integer partial sums
+    double *dpart;     // FP64 partial sums
+    float *axis;       // [4] embedding axis of the current sweep
+    DevRecord *ring;   // per-sweep records
+    // constants of the run
+    uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
+    float x0;                 // O(n): (float)(2J/T)
+    double J;
+    PhiloxKey key;
+    int ring_cap;
+    int mpart_off;  // magnetisation partials start here in ipart / dpart
+    // first block of this replica in each grid of its chain
+    int tile_base, cblk_base, coin_base;
 };
 
-struct IsingParams {
-    uint32_t thr_hi;  // threshold >> 24 (256 when every parallel bond is active)
-    uint32_t thr_lo;  // threshold & 0xFFFFFF
+struct RepState {
+    uint32_t t;         // global index of the next sweep
+    int32_t remaining;  // sweeps still to run in the current call
+    int32_t ring_used;  // records in the ring
+    int32_t e_pending;  // ring slot whose energy is not reduced yet, or -1
+};
+
+// What every chain kernel receives: descriptors, states and the block ->
+// replica maps of the three grids.
+struct Chain {
+    const RepDesc *desc;
+    RepState *const *state;  // state of each replica (in its own workspace)
+    const int *tile_rep;  // tile grid
+    const int *cblk_rep;  // 256-cell blocks
+    const int *coin_rep;  // 256-call blocks of the coin kernel
+    int nreps;
+    int shape;            // TileShape of the tile grid
+    int model;            // 1, 2, 3
+    int ntile_blocks, ncell_blocks, ncoin_blocks;
 };
 
 // Kernel ids for timing.
 enum KernelId : int {
     kKInit = 0,
-    kKBonds,
-    kKUnion,
-    kKFlipTable,
+    kKLocal,
+    kKMerge,
+    kKCoins,
     kKFlip,
     kKEnergy,
     kKFinalize,
     kKAxis,
-    kKProject,
+    kKCompress,
     kNumKernels
 };
 const char *kernel_name(int id);
 
-// Timing hook: the C-ABI layer brackets each launch when enabled.
+// Optional timing hook around each launch (the C-ABI layer brackets
+// launches with HIP events when timing is enabled).
 struct LaunchHook {
     void (*before)(void *ctx, int kernel_id);
     void (*after)(void *ctx, int kernel_id);
     void *ctx;
 };
 
-hipError_t launch_init_ising(const SweepBuffers &b, int start, PhiloxKey key, hipStream_t s);
-hipError_t launch_init_on(const SweepBuffers &b, int n, int start, PhiloxKey key, hipStream_t s);
-hipError_t launch_identity_labels(const SweepBuffers &b, hipStream_t s);
+// Initial state of one replica.
+hipError_t launch_init(const RepDesc &d, int model, int start, hipStream_t st);
+// One sweep of every replica of the chain with remaining > 0.
+hipError_t launch_chain_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook);
+// Energy of the current state into the pending record of every replica of
+// the chain, then mark it complete.
+hipError_t launch_chain_energy_tail(const Chain &c, hipStream_t st, const LaunchHook &hook);
+// Replace every label of one replica by its final root.
+hipError_t launch_compress_labels(const RepDesc &d, hipStream_t st);
 
-// One sweep with global index t; the record goes to ring[slot].
-hipError_t launch_sweep_ising(const SweepBuffers &b, IsingParams p, double J, PhiloxKey key,
-                              uint32_t t, int slot, hipStream_t s, const LaunchHook &hook);
-hipError_t launch_sweep_on(const SweepBuffers &b, int n, float x0, double J, PhiloxKey key,
-                           uint32_t t, int slot, hipStream_t s, const LaunchHook &hook);
+// Sizes of the per-replica partial-sum buffers (any tile shape).
+int64_t ipart_count(int L);
+int64_t dpart_count(int L);
+
+#define PYRO_LAUNCH(id, kernel, grid, block, ...)               \
+    do {                                                        \
+        if ((grid) > 0) {                                       \
+            if (hook.before) hook.before(hook.ctx, id);         \
+            kernel<<<(grid), (block), 0, st>>>(__VA_ARGS__);    \
+            if (hook.after) hook.after(hook.ctx, id);           \
+            hipError_t e_ = hipGetLastError();                  \
+            if (e_ != hipSuccess) return e_;                    \
+        }                                                       \
+    } while (0)
 
 }  // namespace pyro

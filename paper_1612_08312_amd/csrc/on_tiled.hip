@@ -1,0 +1,433 @@
+// XY (n = 2) and Heisenberg (n = 3) Swendsen-Wang sweep on gfx950, with
+// Wolff's embedding (Sec. 2 of the paper): every spin is projected on the
+// sweep's random unit axis r, sigma = s . r; the Ising-like cluster
+// construction runs on the projections, and flipped clusters are reflected
+// through the plane normal to r.
+//
+// Same tile structure and chain of lattices as the Ising sweep
+// (tile_common.hpp, kernels.hpp).  Arithmetic that
+// decides bonds or moves spins is FP32 in a fixed operation order with
+// explicit fused multiply-adds:
+//   sigma = fmaf(s_z, r_z, fmaf(s_y, r_y, s_x * r_x))      (XY: no z term)
+//   x     = (x0 * sigma_a) * sigma_b,   x0 = (float)(2 J / T)
+//   bond active iff (double)x > -log1p(-u), u = (r32 + 0.5) 2^-32, r32 =
+//   word (b mod 4) of Philox(b/4, t, BOND)
+//   reflection s_k <- fmaf(-2 sigma, r_k, s_k)
+// The log1p is evaluated only when x lies between the two bounds
+// u <= -log1p(-u) <= u / (1 - u); outside that window both bounds give the
+// same answer as the exact comparison.  Energies and magnetisations are
+// FP64 sums of the FP32 spins.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "device_util.hpp"
+#include "ising_cell.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "philox.hpp"
+#include "tile_common.hpp"
+#include "unit_vector.hpp"
+
+namespace pyro {
+
+// Embedding axis of the next sweep of every active replica (one thread each).
+__global__ void k_axis(Chain c)
+{
+    const int rep = blockIdx.x;
+    const RepState st = *c.state[rep];
+    if (threadIdx.x != 0 || st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    float r[3];
+    unit_vector(0u, st.t, kStreamAxis, c.model, d.key, r);
+    d.axis[0] = r[0];
+    d.axis[1] = r[1];
+    d.axis[2] = r[2];
+    d.axis[3] = 0.0f;
+}
+
+template <int NV>
+__device__ __forceinline__ float project(const float v[NV], const float r[NV])
+{
+    float sig = __fmul_rn(v[0], r[0]);
+    sig = __fmaf_rn(v[1], r[1], sig);
+    if (NV == 3) sig = __fmaf_rn(v[NV - 1], r[NV - 1], sig);
+    return sig;
+}
+
+// Exact activation decision of one bond (see the file comment).
+__device__ __forceinline__ bool on_bond_active(float x, uint32_t r32)
+{
+    if (!(x > 0.0f)) return false;
+    const double xd = (double)x;
+    const double u = ((double)r32 + 0.5) * 0x1p-32;
+    if (xd <= u) return false;
+    if (xd > u / (1.0 - u) * (1.0 + 1e-13)) return true;
+    return xd > -log1p(-u);
+}
+
+template <int NV, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
+{
+    constexpr int NC = TX * TY * TZ;
+    constexpr int NS = 16 * NC;
+    __shared__ int P[NS];
+    __shared__ uint8_t K4[64];
+    __shared__ double red[16];
+
+    const int rep = c.tile_rep[blockIdx.x];
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int tile = blockIdx.x - d.tile_base;
+    const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
+    const float *__restrict__ s = (const float *)d.spins;
+    const int64_t N = d.N;
+    const float x0 = d.x0;
+    const int tid = threadIdx.x;
+    const int L = d.L;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
+    const bool valid = x < L && y < L && z < L;
+    const int cell = (z * L + y) * L + x;
+    if (tid < 64) {
+        constexpr K4Table k4 = make_k4();
+        K4[tid] = k4.v[tid];
+    }
+
+    uint64_t act = 0;
+    double esum = 0.0;
+    NbrCell nb[kNCellCodes];
+    if (valid) {
+        float r[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
+        ti.neighbours(x, y, z, cell, tid, nb);
+        float own[NV][16];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const float4 *S4 = reinterpret_cast<const float4 *>(s + (int64_t)k * N) + 4 * (int64_t)cell;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = S4[q];
+                own[k][4 * q] = v.x;
+                own[k][4 * q + 1] = v.y;
+                own[k][4 * q + 2] = v.z;
+                own[k][4 * q + 3] = v.w;
+            }
+        }
+        float dv[NV][16];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                const SiteRef R = down_vertex(f, mu);
+#pragma unroll
+                for (int k = 0; k < NV; ++k)
+                    dv[k][4 * f + mu] = R.cell == kSelf ? own[k][R.site]
+                                                        : s[(int64_t)k * N + 16 * nb[R.cell].gcell + R.site];
+            }
+        float sig_own[16], sig_dv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            float a[NV], b[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                a[k] = own[k][q];
+                b[k] = dv[k][q];
+            }
+            sig_own[q] = project<NV>(a, r);
+            sig_dv[q] = project<NV>(b, r);
+        }
+#pragma unroll
+        for (int qg = 0; qg < 12; ++qg) {
+            float xs[4];
+            bool any = false;
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const int j = 4 * qg + k4;
+                const int tet = j / 6, e = j % 6;
+                const int ia = 4 * (tet & 3) + pair_a(e), ib = 4 * (tet & 3) + pair_b(e);
+                const float sa = tet < 4 ? sig_own[ia] : sig_dv[ia];
+                const float sb = tet < 4 ? sig_own[ib] : sig_dv[ib];
+                xs[k4] = __fmul_rn(__fmul_rn(x0, sa), sb);
+                any |= xs[k4] > 0.0f;
+                double dd = 0.0;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    const float va = tet < 4 ? own[k][ia] : dv[k][ia];
+                    const float vb = tet < 4 ? own[k][ib] : dv[k][ib];
+                    dd += (double)va * (double)vb;
+                }
+                esum += dd;
+            }
+            if (any) {
+                const uint4 rnd = philox4x32_10(12u * (uint32_t)cell + qg, st.t, kStreamBond, 0u, d.key);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4)
+                    if (on_bond_active(xs[k4], word_of(rnd, k4))) act |= 1ull << (4 * qg + k4);
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
+        const int base = 16 * tid + 4 * f;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
+    }
+    __syncthreads();
+    if (valid) {
+        uint64_t xm_bits = 0;
+        const uint32_t down = (uint32_t)(act >> 24);
+#pragma unroll
+        for (int jj = 0; jj < 24; ++jj) {
+            if (!((down >> jj) & 1u)) continue;
+            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
+            const int la = nb[A.cell].lcell, lb = nb[B.cell].lcell;
+            if (la >= 0 && lb >= 0)
+                lds_unite<NC>(P, 16 * la + A.site, 16 * lb + B.site);
+            else
+                xm_bits |= 1ull << (24 + jj);
+        }
+        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = xm_bits;
+    }
+    __syncthreads();
+    if (valid) {
+        int rr[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) rr[k] = ti.global_site(lds_find<NC>(P, 16 * tid + k));
+        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_int4(rr[4 * q], rr[4 * q + 1], rr[4 * q + 2], rr[4 * q + 3]);
+    }
+    const double b = block_sum<double>(esum, red);
+    if (tid == 0) d.dpart[tile] = b;
+}
+
+// One thread per cell: roots, coins, reflections, FP64 magnetisation.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_flip_on(Chain c)
+{
+    __shared__ double red[16];
+    const int rep = c.cblk_rep[blockIdx.x];
+    if (c.state[rep]->remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int blk = blockIdx.x - d.cblk_base;
+    const int ncb = blocks_for(d.ncell);
+    const int64_t cl = (int64_t)blk * kBlock + threadIdx.x;
+    const int64_t N = d.N;
+    float *s = (float *)d.spins;
+    const int32_t *__restrict__ label = d.label;
+    const uint32_t *__restrict__ fb = d.coins;
+    double M[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) M[k] = 0.0;
+    if (cl < d.ncell) {
+        float r[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
+        const int4 *L4 = reinterpret_cast<const int4 *>(label + 16 * cl);
+        int lab[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 v = L4[q];
+            lab[4 * q] = v.x;
+            lab[4 * q + 1] = v.y;
+            lab[4 * q + 2] = v.z;
+            lab[4 * q + 3] = v.w;
+        }
+        int last_in = -1, last_root = -1;
+        uint32_t flipmask = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int rt = lab[k];
+            if (rt != last_in) {
+                last_in = rt;
+                rt = uf_find(label, rt);
+                last_root = rt;
+            } else {
+                rt = last_root;
+            }
+            flipmask |= ((fb[rt >> 5] >> (rt & 31)) & 1u) << k;
+        }
+        float v[NV][16];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const float4 *S4 = reinterpret_cast<const float4 *>(s + (int64_t)k * N) + 4 * cl;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 a = S4[q];
+                v[k][4 * q] = a.x;
+                v[k][4 * q + 1] = a.y;
+                v[k][4 * q + 2] = a.z;
+                v[k][4 * q + 3] = a.w;
+            }
+        }
+        if (flipmask) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                if (!((flipmask >> q) & 1u)) continue;
+                float a[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) a[k] = v[k][q];
+                const float cc = -2.0f * project<NV>(a, r);
+#pragma unroll
+                for (int k = 0; k < NV; ++k) v[k][q] = __fmaf_rn(cc, r[k], v[k][q]);
+            }
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                float4 *S4 = reinterpret_cast<float4 *>(s + (int64_t)k * N) + 4 * cl;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    S4[q] = make_float4(v[k][4 * q], v[k][4 * q + 1], v[k][4 * q + 2], v[k][4 * q + 3]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) M[k] += (double)v[k][q];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double b = block_sum<double>(M[k], red);
+        if (threadIdx.x == 0) d.dpart[d.mpart_off + (int64_t)k * ncb + blk] = b;
+    }
+}
+
+// Records and state (see k_finalize_ising).
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_finalize_on(Chain c)
+{
+    __shared__ double red[16];
+    const int rep = blockIdx.x;
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int ntiles = d.ntx * d.nty * d.ntz;
+    const int ncb = blocks_for(d.ncell);
+    double E = 0.0;
+    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) E += d.dpart[k];
+    E = block_sum<double>(E, red);
+    double M[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < ncb; k += blockDim.x) v += d.dpart[d.mpart_off + (int64_t)q * ncb + k];
+        M[q] = block_sum<double>(v, red);
+    }
+    if (threadIdx.x == 0) {
+        if (st.e_pending >= 0) d.ring[st.e_pending].E = -d.J * E;
+        const int slot = st.ring_used;
+        if (slot < d.ring_cap) {
+            DevRecord rec;
+            rec.sweep = st.t;
+            rec.bond_sum = 0;
+            rec.M_int = 0;
+            rec.reserved = 0;
+            rec.E = 0.0;
+            rec.M[0] = M[0];
+            rec.M[1] = M[1];
+            rec.M[2] = M[2];
+            const double m = sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]) / (double)d.N;
+            rec.m2 = m * m;
+            rec.m4 = rec.m2 * rec.m2;
+            d.ring[slot] = rec;
+        }
+        RepState ns;
+        ns.t = st.t + 1;
+        ns.remaining = st.remaining - 1;
+        ns.ring_used = slot + 1;
+        ns.e_pending = slot < d.ring_cap ? slot : -1;
+        *c.state[rep] = ns;
+    }
+}
+
+// Energy of the current state for replicas whose last record is pending.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_energy_on(Chain c)
+{
+    __shared__ double red[16];
+    const int rep = c.cblk_rep[blockIdx.x];
+    if (c.state[rep]->e_pending < 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int blk = blockIdx.x - d.cblk_base;
+    const int64_t cl = (int64_t)blk * kBlock + threadIdx.x;
+    const float *__restrict__ s = (const float *)d.spins;
+    const int64_t N = d.N;
+    double esum = 0.0;
+    if (cl < d.ncell) {
+        const CellNbrs nb = cell_neighbours((int)cl, d.L);
+#pragma unroll
+        for (int j = 0; j < 48; ++j) {
+            const SiteRef A = bond_end_a(j), B = bond_end_b(j);
+            const int64_t ia = 16 * (int64_t)nb.c[A.cell] + A.site, ib = 16 * (int64_t)nb.c[B.cell] + B.site;
+            double dd = 0.0;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) dd += (double)s[k * N + ia] * (double)s[k * N + ib];
+            esum += dd;
+        }
+    }
+    const double b = block_sum<double>(esum, red);
+    if (threadIdx.x == 0) d.dpart[d.mpart_off + blk] = b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_tail_finalize_on(Chain c)
+{
+    __shared__ double red[16];
+    const int rep = blockIdx.x;
+    const RepState st = *c.state[rep];
+    if (st.e_pending < 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int ncb = blocks_for(d.ncell);
+    double E = 0.0;
+    for (int k = threadIdx.x; k < ncb; k += blockDim.x) E += d.dpart[d.mpart_off + k];
+    E = block_sum<double>(E, red);
+    if (threadIdx.x == 0) {
+        d.ring[st.e_pending].E = -d.J * E;
+        c.state[rep]->e_pending = -1;
+    }
+}
+
+template <int NV>
+struct OnLocal {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
+    {
+        PYRO_LAUNCH(kKLocal, (k_local_on<NV, TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        return hipSuccess;
+    }
+};
+
+template <int NV>
+static hipError_t sweep_on(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    PYRO_LAUNCH(kKAxis, k_axis, c.nreps, 64, c);
+    hipError_t e = with_tile_shape<OnLocal<NV>>(c.shape, c, st, hook);
+    if (e == hipSuccess) e = launch_merge(c, st, hook);
+    if (e == hipSuccess) e = launch_coins(c, st, hook);
+    if (e != hipSuccess) return e;
+    PYRO_LAUNCH(kKFlip, k_flip_on<NV>, c.ncell_blocks, kBlock, c);
+    PYRO_LAUNCH(kKFinalize, k_finalize_on<NV>, c.nreps, kBlock, c);
+    return hipSuccess;
+}
+
+hipError_t launch_on_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    return c.model == 2 ? sweep_on<2>(c, st, hook) : sweep_on<3>(c, st, hook);
+}
+
+template <int NV>
+static hipError_t energy_tail_on(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    PYRO_LAUNCH(kKEnergy, k_energy_on<NV>, c.ncell_blocks, kBlock, c);
+    PYRO_LAUNCH(kKFinalize, k_energy_tail_finalize_on, c.nreps, kBlock, c);
+    return hipSuccess;
+}
+
+hipError_t launch_on_energy_tail(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    return c.model == 2 ? energy_tail_on<2>(c, st, hook) : energy_tail_on<3>(c, st, hook);
+}
+
+}  // namespace pyro

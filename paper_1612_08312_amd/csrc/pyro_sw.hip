@@ -1,16 +1,21 @@
 // C-ABI layer of the pyrochlore Swendsen-Wang library (declared in
-// include/pyro_sw.h): argument checks, device memory, the per-sweep record
-// ring, kernel timing and error state.  No arithmetic of the method lives
-// here except the two per-run constants of Sec. 2 that every kernel reads:
-// the Ising activation threshold floor((1 - exp(-2J/T)) 2^32) and the O(n)
-// coupling x0 = (float)(2J/T).
+// include/pyro_sw.h): argument checks, device memory, replica descriptors,
+// groups of lattices swept together from one captured graph, the tile-shape
+// autotuner, the per-sweep record rings, kernel timing and error state.
+//
+// No arithmetic of the method lives here except the two per-run constants of
+// Sec. 2 that the kernels read: the Ising activation threshold
+// floor((1 - exp(-2J/T)) 2^32) and the O(n) coupling x0 = (float)(2J/T).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <deque>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -33,40 +38,56 @@ int fail(int status, const std::string &msg)
     return status;
 }
 
-constexpr int64_t kRing = 16384;  // device records before a forced drain
+constexpr int kRing = 16384;  // device records per lattice before a forced drain
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+int64_t tiles_for(int L, int shape)
+{
+    const TileDims t = tile_dims(shape);
+    return (int64_t)((L + t.x - 1) / t.x) * ((L + t.y - 1) / t.y) * ((L + t.z - 1) / t.z);
+}
+
+int64_t max_tiles(int L)
+{
+    int64_t m = 0;
+    for (int s = 0; s < kNumTileShapes; ++s) m = std::max(m, tiles_for(L, s));
+    return m;
+}
+
+int64_t coin_calls(int64_t N) { return (N + 127) / 128; }
+
 struct Layout {
-    size_t spin_bytes, label, mask, flip, sigma, axis, ipart, dpart, ring, total;
+    size_t spin_bytes;
+    size_t label, xmask, coins, ipart, dpart, axis, ring, state, solo_desc, solo_stp, solo_map, total;
+    int64_t map_len;
 };
 
 Layout layout_for(int L, int model)
 {
     const int64_t ncell = (int64_t)L * L * L;
     const int64_t N = 16 * ncell;
-    const int n = model;
     Layout ly{};
-    ly.spin_bytes = align_up(model == PYRO_ISING ? (size_t)N : sizeof(float) * (size_t)n * N);
+    ly.spin_bytes = align_up(model == PYRO_ISING ? (size_t)N : sizeof(float) * (size_t)model * N);
     size_t off = 0;
-    ly.label = off;
-    off += align_up(sizeof(int32_t) * (size_t)N);
-    ly.mask = off;
-    off += align_up(sizeof(uint64_t) * (size_t)ncell);
-    ly.flip = off;
-    off += align_up(16 * (size_t)((N + 127) / 128));
-    ly.sigma = off;
-    off += model == PYRO_ISING ? 0 : align_up(sizeof(float) * (size_t)N);
-    ly.axis = off;
-    off += kAlign;
-    const int64_t nblk = blocks_for(ncell);
-    ly.ipart = off;
-    off += align_up(sizeof(int64_t) * 2 * (size_t)nblk);
-    ly.dpart = off;
-    off += model == PYRO_ISING ? 0 : align_up(sizeof(double) * 4 * (size_t)nblk);
-    ly.ring = off;
-    off += align_up(sizeof(pyro_sw_record) * (size_t)kRing);
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
+    ly.label = take(sizeof(int32_t) * (size_t)N);
+    ly.xmask = take(sizeof(uint64_t) * (size_t)ncell);
+    ly.coins = take(16 * (size_t)coin_calls(N));
+    ly.ipart = take(sizeof(int64_t) * (size_t)ipart_count(L));
+    ly.dpart = take(model == PYRO_ISING ? 0 : sizeof(double) * (size_t)dpart_count(L));
+    ly.axis = take(4 * sizeof(float));
+    ly.ring = take(sizeof(pyro_sw_record) * (size_t)kRing);
+    ly.state = take(sizeof(RepState));
+    ly.solo_desc = take(sizeof(RepDesc));
+    ly.solo_stp = take(sizeof(RepState *));
+    ly.map_len = std::max<int64_t>({max_tiles(L), blocks_for(ncell), blocks_for(coin_calls(N))});
+    ly.solo_map = take(sizeof(int) * (size_t)ly.map_len);
     ly.total = off;
     return ly;
 }
@@ -87,6 +108,95 @@ struct TimedLaunch {
     hipEvent_t e0, e1;
 };
 
+// Kernel timing with HIP events (handles and groups each own one).
+struct Timer {
+    int mask = 0;
+    hipStream_t stream = nullptr;
+    std::vector<TimedLaunch> inflight;
+    std::vector<hipEvent_t> pool;
+    double ms[kNumKernels] = {};
+    int64_t launches[kNumKernels] = {};
+
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    static void before(void *ctx, int id)
+    {
+        Timer *t = (Timer *)ctx;
+        if (!((t->mask >> id) & 1)) return;
+        TimedLaunch tl{id, t->take(), t->take()};
+        if (tl.e0 && tl.e1) {
+            hipEventRecord(tl.e0, t->stream);
+            t->inflight.push_back(tl);
+        }
+    }
+    static void after(void *ctx, int id)
+    {
+        Timer *t = (Timer *)ctx;
+        if (!((t->mask >> id) & 1)) return;
+        if (!t->inflight.empty() && t->inflight.back().id == id) hipEventRecord(t->inflight.back().e1, t->stream);
+    }
+    LaunchHook hook() { return LaunchHook{before, after, this}; }
+    hipError_t collect()
+    {
+        if (inflight.empty()) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        for (auto &tl : inflight) {
+            float v = 0.f;
+            e = hipEventElapsedTime(&v, tl.e0, tl.e1);
+            if (e != hipSuccess) return e;
+            ms[tl.id] += v;
+            launches[tl.id] += 1;
+            pool.push_back(tl.e0);
+            pool.push_back(tl.e1);
+        }
+        inflight.clear();
+        return hipSuccess;
+    }
+    void reset(int m)
+    {
+        mask = m;
+        for (int k = 0; k < kNumKernels; ++k) {
+            ms[k] = 0.0;
+            launches[k] = 0;
+        }
+    }
+    void release()
+    {
+        for (auto &tl : inflight) {
+            hipEventDestroy(tl.e0);
+            hipEventDestroy(tl.e1);
+        }
+        inflight.clear();
+        for (auto e : pool) hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
+// Chain tables in device memory for a list of replicas of one model.
+struct ChainTables {
+    int model = 0, shape = kTile884;
+    std::vector<pyro_sw *> reps;
+    RepDesc *d_desc = nullptr;
+    RepState **d_stp = nullptr;
+    int *d_tile_rep = nullptr, *d_cblk_rep = nullptr, *d_coin_rep = nullptr;
+    Chain chain{};
+    bool owned = true;  // tables allocated with hipMalloc (groups) or in a workspace (solo)
+};
+
+// Process-wide autotuning results: (model, multiset of L) -> tile shape.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
 }  // namespace
 
 struct pyro_sw {
@@ -95,39 +205,55 @@ struct pyro_sw {
     double T = 0, J = 0;
     uint64_t seed = 0;
     int start = 0;
-    IsingParams ip{};
+    uint32_t thr_hi = 0, thr_lo = 0;
     float x0 = 0;
     hipStream_t stream = nullptr;
-    bool own_stream = false;
-    bool own_mem = false;
+    bool own_stream = false, own_mem = false;
     void *spins = nullptr;
     char *work = nullptr;
     Layout ly{};
-    SweepBuffers buf{};
-    int64_t ring_used = 0;
+    RepState *d_state = nullptr;
+    // host mirror of the device state (the kernels advance it deterministically)
+    RepState hs{};
     std::deque<pyro_sw_record> host_q;
-    int64_t t = 0;
     bool broken = false;
-    // timing
-    int timing = 0;  // bit mask of timed kernel ids
-    std::vector<TimedLaunch> inflight;
-    std::vector<hipEvent_t> pool;
-    double ms[kNumKernels] = {};
-    int64_t launches[kNumKernels] = {};
+    int busy = 0;  // nonzero while a group sweeps this lattice
+    // solo sweeps
+    ChainTables solo;
+    int solo_shape = kTile884;
+    hipGraphExec_t solo_exec = nullptr;
+    uint64_t param_version = 1, solo_version = 0;
+    Timer timer;
+};
+
+struct pyro_sw_group {
+    std::vector<pyro_sw *> members;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    ChainTables chains[3];  // Ising, XY, Heisenberg
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> seen_versions;
+    bool tables_dirty = true;
+    RepState **d_members = nullptr;  // state pointer of every member
+    RepState *d_staged = nullptr;
+    RepState *h_staged = nullptr;  // pinned
+    bool broken = false;
+    Timer timer;
 };
 
 namespace {
 
-int device_fail(pyro_sw *h, hipError_t e, const char *what)
+int device_fail(bool *broken, hipError_t e, const char *what)
 {
-    if (h) h->broken = true;
+    if (broken) *broken = true;
+    (void)hipGetLastError();
     return fail(PYRO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_OR_FAIL(h, call)                                 \
-    do {                                                     \
-        hipError_t e__ = (call);                             \
-        if (e__ != hipSuccess) return device_fail(h, e__, #call); \
+#define HIP_OR_FAIL(flag, call)                                          \
+    do {                                                                 \
+        hipError_t e__ = (call);                                         \
+        if (e__ != hipSuccess) return device_fail(flag, e__, #call);     \
     } while (0)
 
 void set_params(pyro_sw *h, double T)
@@ -136,66 +262,206 @@ void set_params(pyro_sw *h, double T)
     const double twobj = 2.0 * h->J / T;
     const double p = -expm1(-twobj);
     const uint64_t thr = (uint64_t)floor(p * 4294967296.0);
-    h->ip.thr_hi = (uint32_t)(thr >> 24);
-    h->ip.thr_lo = (uint32_t)(thr & 0xFFFFFFu);
+    h->thr_hi = (uint32_t)(thr >> 24);
+    h->thr_lo = (uint32_t)(thr & 0xFFFFFFu);
     h->x0 = (float)twobj;
+    h->param_version++;
 }
 
-hipEvent_t take_event(pyro_sw *h)
+// Descriptor of a replica for a chain with tile shape `shape`.
+RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int coin_base)
 {
-    if (!h->pool.empty()) {
-        hipEvent_t e = h->pool.back();
-        h->pool.pop_back();
-        return e;
+    RepDesc d{};
+    const TileDims t = tile_dims(shape);
+    d.L = h->L;
+    d.ntx = (h->L + t.x - 1) / t.x;
+    d.nty = (h->L + t.y - 1) / t.y;
+    d.ntz = (h->L + t.z - 1) / t.z;
+    d.ncell = h->ncell;
+    d.N = h->N;
+    d.spins = h->spins;
+    d.label = (int32_t *)(h->work + h->ly.label);
+    d.xmask = (uint64_t *)(h->work + h->ly.xmask);
+    d.coins = (uint32_t *)(h->work + h->ly.coins);
+    d.ipart = (int64_t *)(h->work + h->ly.ipart);
+    d.dpart = h->model == PYRO_ISING ? nullptr : (double *)(h->work + h->ly.dpart);
+    d.axis = (float *)(h->work + h->ly.axis);
+    d.ring = (DevRecord *)(h->work + h->ly.ring);
+    d.thr_hi = h->thr_hi;
+    d.thr_lo = h->thr_lo;
+    d.x0 = h->x0;
+    d.J = h->J;
+    d.key = philox_key(h->seed);
+    d.ring_cap = kRing;
+    d.mpart_off = (int)max_tiles(h->L);
+    d.tile_base = tile_base;
+    d.cblk_base = cblk_base;
+    d.coin_base = coin_base;
+    return d;
+}
+
+void free_tables(ChainTables &ct)
+{
+    if (ct.owned) {
+        hipFree(ct.d_desc);
+        hipFree(ct.d_stp);
+        hipFree(ct.d_tile_rep);
+        hipFree(ct.d_cblk_rep);
+        hipFree(ct.d_coin_rep);
     }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ct.d_desc = nullptr;
+    ct.d_stp = nullptr;
+    ct.d_tile_rep = ct.d_cblk_rep = ct.d_coin_rep = nullptr;
+}
+
+// Build (or rebuild) the device tables of a group chain (synchronous copies).
+hipError_t build_group_chain(ChainTables &ct, int shape)
+{
+    free_tables(ct);
+    ct.owned = true;
+    ct.shape = shape;
+    const int n = (int)ct.reps.size();
+    ct.chain = Chain{};
+    ct.chain.nreps = n;
+    ct.chain.model = ct.model;
+    ct.chain.shape = shape;
+    if (n == 0) return hipSuccess;
+    std::vector<RepDesc> desc(n);
+    std::vector<RepState *> stp(n);
+    std::vector<int> tmap, cmap, kmap;
+    int tb = 0, cb = 0, kb = 0;
+    for (int r = 0; r < n; ++r) {
+        pyro_sw *h = ct.reps[r];
+        desc[r] = make_desc(h, shape, tb, cb, kb);
+        stp[r] = h->d_state;
+        const int nt = (int)tiles_for(h->L, shape), nc = blocks_for(h->ncell), nk = blocks_for(coin_calls(h->N));
+        tmap.insert(tmap.end(), nt, r);
+        cmap.insert(cmap.end(), nc, r);
+        kmap.insert(kmap.end(), nk, r);
+        tb += nt;
+        cb += nc;
+        kb += nk;
+    }
+    hipError_t e;
+    if ((e = hipMalloc((void **)&ct.d_desc, sizeof(RepDesc) * n)) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&ct.d_stp, sizeof(RepState *) * n)) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&ct.d_tile_rep, sizeof(int) * tmap.size())) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&ct.d_cblk_rep, sizeof(int) * cmap.size())) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&ct.d_coin_rep, sizeof(int) * kmap.size())) != hipSuccess) return e;
+    if ((e = hipMemcpy(ct.d_desc, desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(ct.d_stp, stp.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(ct.d_tile_rep, tmap.data(), sizeof(int) * tmap.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpy(ct.d_cblk_rep, cmap.data(), sizeof(int) * cmap.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpy(ct.d_coin_rep, kmap.data(), sizeof(int) * kmap.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    ct.chain.desc = ct.d_desc;
+    ct.chain.state = ct.d_stp;
+    ct.chain.tile_rep = ct.d_tile_rep;
+    ct.chain.cblk_rep = ct.d_cblk_rep;
+    ct.chain.coin_rep = ct.d_coin_rep;
+    ct.chain.ntile_blocks = tb;
+    ct.chain.ncell_blocks = cb;
+    ct.chain.ncoin_blocks = kb;
+    return hipSuccess;
+}
+
+// Solo chain: tables inside the handle's workspace (block maps all zero).
+hipError_t build_solo_chain(pyro_sw *h)
+{
+    ChainTables &ct = h->solo;
+    ct.owned = false;
+    ct.model = h->model;
+    ct.shape = h->solo_shape;
+    ct.reps.assign(1, h);
+    const RepDesc d = make_desc(h, h->solo_shape, 0, 0, 0);
+    ct.d_desc = (RepDesc *)(h->work + h->ly.solo_desc);
+    ct.d_stp = (RepState **)(h->work + h->ly.solo_stp);
+    int *zeros = (int *)(h->work + h->ly.solo_map);
+    ct.d_tile_rep = ct.d_cblk_rep = ct.d_coin_rep = zeros;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    if ((e = hipMemcpy(ct.d_desc, &d, sizeof(RepDesc), hipMemcpyHostToDevice)) != hipSuccess) return e;
+    RepState *p = h->d_state;
+    if ((e = hipMemcpy(ct.d_stp, &p, sizeof(p), hipMemcpyHostToDevice)) != hipSuccess) return e;
+    Chain &c = ct.chain;
+    c = Chain{};
+    c.desc = ct.d_desc;
+    c.state = ct.d_stp;
+    c.tile_rep = c.cblk_rep = c.coin_rep = zeros;
+    c.nreps = 1;
+    c.shape = h->solo_shape;
+    c.model = h->model;
+    c.ntile_blocks = (int)tiles_for(h->L, h->solo_shape);
+    c.ncell_blocks = blocks_for(h->ncell);
+    c.ncoin_blocks = blocks_for(coin_calls(h->N));
+    if (h->solo_exec) {
+        hipGraphExecDestroy(h->solo_exec);
+        h->solo_exec = nullptr;
+    }
+    h->solo_version = h->param_version;
+    return hipSuccess;
+}
+
+// Capture one sweep of the given chains on a private stream (nothing runs);
+// the executable graph is later launched on the caller's stream.
+hipError_t capture_sweep(const Chain *chains, int nchains, hipGraphExec_t *exec)
+{
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    const LaunchHook none{nullptr, nullptr, nullptr};
+    hipError_t le = hipSuccess;
+    if (e == hipSuccess) {
+        for (int k = 0; k < nchains && le == hipSuccess; ++k) le = launch_chain_sweep(chains[k], cs, none);
+        e = hipStreamEndCapture(cs, &graph);
+    }
+    if (e == hipSuccess && le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    hipStreamDestroy(cs);
     return e;
 }
 
-void hook_before(void *ctx, int id)
+// Copy staged states into the replicas' device states, in stream order.
+__global__ void k_arm(RepState *const *stp, const RepState *staged, int n)
 {
-    pyro_sw *h = (pyro_sw *)ctx;
-    if (!((h->timing >> id) & 1)) return;
-    TimedLaunch tl{id, take_event(h), take_event(h)};
-    if (tl.e0 && tl.e1) {
-        hipEventRecord(tl.e0, h->stream);
-        h->inflight.push_back(tl);
-    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *stp[i] = staged[i];
 }
 
-void hook_after(void *ctx, int id)
+int usable(const pyro_sw *h)
 {
-    pyro_sw *h = (pyro_sw *)ctx;
-    if (!h->inflight.empty() && h->inflight.back().id == id) hipEventRecord(h->inflight.back().e1, h->stream);
-}
-
-// Fold completed timed launches into the totals (synchronises).
-int collect_timing(pyro_sw *h)
-{
-    if (h->inflight.empty()) return PYRO_OK;
-    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-    for (auto &tl : h->inflight) {
-        float ms = 0.f;
-        HIP_OR_FAIL(h, hipEventElapsedTime(&ms, tl.e0, tl.e1));
-        h->ms[tl.id] += ms;
-        h->launches[tl.id] += 1;
-        h->pool.push_back(tl.e0);
-        h->pool.push_back(tl.e1);
-    }
-    h->inflight.clear();
+    if (!h) return fail(PYRO_EINVAL, "handle is NULL");
+    if (h->broken) return fail(PYRO_ESTATE, "handle failed earlier");
+    if (h->busy) return fail(PYRO_ESTATE, "handle is sweeping inside a group");
     return PYRO_OK;
 }
 
+LaunchHook hook_of(Timer &tm, hipStream_t st)
+{
+    tm.stream = st;
+    return tm.mask ? tm.hook() : LaunchHook{nullptr, nullptr, nullptr};
+}
+
+// Energy of the pending record (tail), then copy the ring to the host queue.
 int drain(pyro_sw *h)
 {
-    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-    if (h->ring_used > 0) {
-        std::vector<pyro_sw_record> tmp((size_t)h->ring_used);
-        HIP_OR_FAIL(h, hipMemcpy(tmp.data(), h->buf.ring, sizeof(pyro_sw_record) * tmp.size(),
-                                 hipMemcpyDeviceToHost));
+    if (h->hs.e_pending >= 0) {
+        if (h->solo_version != h->param_version) HIP_OR_FAIL(&h->broken, build_solo_chain(h));
+        HIP_OR_FAIL(&h->broken, launch_chain_energy_tail(h->solo.chain, h->stream, hook_of(h->timer, h->stream)));
+        h->hs.e_pending = -1;
+    }
+    HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
+    if (h->hs.ring_used > 0) {
+        std::vector<pyro_sw_record> tmp((size_t)h->hs.ring_used);
+        HIP_OR_FAIL(&h->broken, hipMemcpy(tmp.data(), h->work + h->ly.ring, sizeof(pyro_sw_record) * tmp.size(),
+                                          hipMemcpyDeviceToHost));
         for (auto &r : tmp) h->host_q.push_back(r);
-        h->ring_used = 0;
+        h->hs.ring_used = 0;
     }
     return PYRO_OK;
 }
@@ -207,7 +473,7 @@ int create(pyro_sw **out, int L, int model, double T, double J, uint64_t seed, i
     *out = nullptr;
     int rc = check_args(L, model, T, J, start);
     if (rc) return rc;
-    Layout ly = layout_for(L, model);
+    const Layout ly = layout_for(L, model);
     if (ext) {
         if (!dev_spins || !dev_work) return fail(PYRO_EINVAL, "device buffers must not be NULL");
         if (((uintptr_t)dev_spins % kAlign) || ((uintptr_t)dev_work % kAlign))
@@ -243,7 +509,7 @@ int create(pyro_sw **out, int L, int model, double T, double J, uint64_t seed, i
         hipError_t e1 = hipMalloc(&h->spins, ly.spin_bytes);
         hipError_t e2 = e1 == hipSuccess ? hipMalloc((void **)&h->work, ly.total) : e1;
         if (e1 != hipSuccess || e2 != hipSuccess) {
-            if (h->spins && e1 == hipSuccess) hipFree(h->spins);
+            if (e1 == hipSuccess) hipFree(h->spins);
             if (h->own_stream) hipStreamDestroy(h->stream);
             delete h;
             (void)hipGetLastError();
@@ -251,23 +517,15 @@ int create(pyro_sw **out, int L, int model, double T, double J, uint64_t seed, i
         }
         h->own_mem = true;
     }
-    SweepBuffers &b = h->buf;
-    b.L = L;
-    b.ncell = h->ncell;
-    b.N = h->N;
-    b.spins = h->spins;
-    b.label = (int32_t *)(h->work + ly.label);
-    b.mask = (uint64_t *)(h->work + ly.mask);
-    b.flipbits = (uint32_t *)(h->work + ly.flip);
-    b.sigma = model == PYRO_ISING ? nullptr : (float *)(h->work + ly.sigma);
-    b.axis = (float *)(h->work + ly.axis);
-    b.ipart = (int64_t *)(h->work + ly.ipart);
-    b.dpart = model == PYRO_ISING ? nullptr : (double *)(h->work + ly.dpart);
-    b.ring = (DevRecord *)(h->work + ly.ring);
-    const PhiloxKey key = philox_key(seed);
-    hipError_t e = model == PYRO_ISING ? launch_init_ising(b, start, key, h->stream)
-                                       : launch_init_on(b, model, start, key, h->stream);
-    if (e == hipSuccess) e = launch_identity_labels(b, h->stream);
+    h->d_state = (RepState *)(h->work + ly.state);
+    h->hs = RepState{0u, 0, 0, -1};
+    std::vector<int> zeros((size_t)ly.map_len, 0);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->work + ly.solo_map, zeros.data(), sizeof(int) * zeros.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_state, &h->hs, sizeof(RepState), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = build_solo_chain(h);
+    if (e == hipSuccess) e = launch_init(make_desc(h, h->solo_shape, 0, 0, 0), model, start, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         int r = fail(PYRO_EDEVICE, std::string("initial state: ") + hipGetErrorString(e));
@@ -278,11 +536,21 @@ int create(pyro_sw **out, int L, int model, double T, double J, uint64_t seed, i
     return PYRO_OK;
 }
 
-int usable(const pyro_sw *h)
+// Before a call that runs up to `n` more sweeps of h: room in the ring.
+int make_room(pyro_sw *h, int64_t n)
 {
-    if (!h) return fail(PYRO_EINVAL, "handle is NULL");
-    if (h->broken) return fail(PYRO_ESTATE, "handle failed earlier");
+    if (h->hs.ring_used + n > kRing) return drain(h);
     return PYRO_OK;
+}
+
+std::string tune_key(const ChainTables &ct)
+{
+    std::vector<int> Ls;
+    for (auto *r : ct.reps) Ls.push_back(r->L);
+    std::sort(Ls.begin(), Ls.end());
+    std::string k = "m" + std::to_string(ct.model) + ":";
+    for (int L : Ls) k += std::to_string(L) + ",";
+    return k;
 }
 
 }  // namespace
@@ -293,7 +561,7 @@ int pyro_sw_workspace_size(int L, int model, size_t *spin_bytes, size_t *work_by
 {
     if (L < 1 || L > 447) return fail(PYRO_EINVAL, "L must be in [1, 447]");
     if (model < PYRO_ISING || model > PYRO_HEISENBERG) return fail(PYRO_EINVAL, "model must be 1, 2 or 3");
-    Layout ly = layout_for(L, model);
+    const Layout ly = layout_for(L, model);
     if (spin_bytes) *spin_bytes = ly.spin_bytes;
     if (work_bytes) *work_bytes = ly.total;
     return PYRO_OK;
@@ -315,30 +583,34 @@ int pyro_sw_sweep(pyro_sw *h, int64_t n_sweeps)
     int rc = usable(h);
     if (rc) return rc;
     if (n_sweeps < 0) return fail(PYRO_EINVAL, "n_sweeps must be >= 0");
-    if (h->t + n_sweeps > (int64_t)UINT32_MAX) return fail(PYRO_EINVAL, "sweep index would exceed 2^32 - 1");
-    const PhiloxKey key = philox_key(h->seed);
-    LaunchHook hook{nullptr, nullptr, h};
-    if (h->timing) {
-        hook.before = hook_before;
-        hook.after = hook_after;
-    }
-    for (int64_t k = 0; k < n_sweeps; ++k) {
-        if (h->ring_used == kRing) {
-            rc = drain(h);
-            if (rc) return rc;
+    if ((int64_t)h->hs.t + n_sweeps > (int64_t)UINT32_MAX)
+        return fail(PYRO_EINVAL, "sweep index would exceed 2^32 - 1");
+    Timer &tm = h->timer;
+    while (n_sweeps > 0) {
+        const int64_t chunk = std::min<int64_t>(n_sweeps, kRing);
+        rc = make_room(h, chunk);
+        if (rc) return rc;
+        if (h->solo_version != h->param_version) HIP_OR_FAIL(&h->broken, build_solo_chain(h));
+        RepState armed = h->hs;
+        armed.remaining = (int32_t)chunk;
+        HIP_OR_FAIL(&h->broken, hipMemcpyAsync(h->d_state, &armed, sizeof(RepState), hipMemcpyHostToDevice,
+                                               h->stream));
+        if (tm.mask) {
+            const LaunchHook hook = hook_of(tm, h->stream);
+            for (int64_t k = 0; k < chunk; ++k) {
+                HIP_OR_FAIL(&h->broken, launch_chain_sweep(h->solo.chain, h->stream, hook));
+                if (tm.inflight.size() > 8192) HIP_OR_FAIL(&h->broken, tm.collect());
+            }
+        } else {
+            if (!h->solo_exec) HIP_OR_FAIL(&h->broken, capture_sweep(&h->solo.chain, 1, &h->solo_exec));
+            for (int64_t k = 0; k < chunk; ++k) HIP_OR_FAIL(&h->broken, hipGraphLaunch(h->solo_exec, h->stream));
         }
-        if (h->timing && h->inflight.size() > 8192) {
-            rc = collect_timing(h);
-            if (rc) return rc;
-        }
-        const uint32_t t = (uint32_t)h->t;
-        hipError_t e = h->model == PYRO_ISING
-                           ? launch_sweep_ising(h->buf, h->ip, h->J, key, t, (int)h->ring_used, h->stream, hook)
-                           : launch_sweep_on(h->buf, h->model, h->x0, h->J, key, t, (int)h->ring_used,
-                                             h->stream, hook);
-        if (e != hipSuccess) return device_fail(h, e, "sweep launch");
-        h->ring_used++;
-        h->t++;
+        // mirror what the kernels did to the device state
+        h->hs.t += (uint32_t)chunk;
+        h->hs.ring_used += (int32_t)chunk;
+        h->hs.e_pending = h->hs.ring_used - 1;
+        h->hs.remaining = 0;
+        n_sweeps -= chunk;
     }
     return PYRO_OK;
 }
@@ -369,8 +641,8 @@ int pyro_sw_get_spins(pyro_sw *h, void *host, size_t bytes)
     if (rc) return rc;
     const size_t need = h->model == PYRO_ISING ? (size_t)h->N : sizeof(float) * h->model * (size_t)h->N;
     if (!host || bytes != need) return fail(PYRO_EINVAL, "host buffer size must equal the spin array size");
-    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-    HIP_OR_FAIL(h, hipMemcpy(host, h->spins, need, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
+    HIP_OR_FAIL(&h->broken, hipMemcpy(host, h->spins, need, hipMemcpyDeviceToHost));
     return PYRO_OK;
 }
 
@@ -386,10 +658,9 @@ int pyro_sw_set_spins(pyro_sw *h, const void *host, size_t bytes, int64_t next_s
         for (int64_t i = 0; i < h->N; ++i)
             if (s[i] != 1 && s[i] != -1) return fail(PYRO_EINVAL, "Ising spins must be +1 or -1");
     }
-    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-    HIP_OR_FAIL(h, hipMemcpy(h->spins, host, need, hipMemcpyHostToDevice));
-    h->t = next_sweep;
-    h->ring_used = 0;
+    HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
+    HIP_OR_FAIL(&h->broken, hipMemcpy(h->spins, host, need, hipMemcpyHostToDevice));
+    h->hs = RepState{(uint32_t)next_sweep, 0, 0, -1};
     h->host_q.clear();
     return PYRO_OK;
 }
@@ -399,8 +670,10 @@ int pyro_sw_get_labels(pyro_sw *h, int32_t *host, size_t n)
     int rc = usable(h);
     if (rc) return rc;
     if (!host || n != (size_t)h->N) return fail(PYRO_EINVAL, "n must equal N");
-    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-    HIP_OR_FAIL(h, hipMemcpy(host, h->buf.label, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    const RepDesc d = make_desc(h, h->solo_shape, 0, 0, 0);
+    HIP_OR_FAIL(&h->broken, launch_compress_labels(d, h->stream));
+    HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
+    HIP_OR_FAIL(&h->broken, hipMemcpy(host, d.label, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     return PYRO_OK;
 }
 
@@ -413,11 +686,21 @@ int pyro_sw_set_temperature(pyro_sw *h, double T)
     return PYRO_OK;
 }
 
+int pyro_sw_set_tile_shape(pyro_sw *h, int shape)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (shape < 0 || shape >= kNumTileShapes) return fail(PYRO_EINVAL, "unknown tile shape");
+    h->solo_shape = shape;
+    h->param_version++;
+    return PYRO_OK;
+}
+
 int pyro_sw_info(const pyro_sw *h, int64_t *n_sites, int64_t *next_sweep)
 {
     if (!h) return fail(PYRO_EINVAL, "handle is NULL");
     if (n_sites) *n_sites = h->N;
-    if (next_sweep) *next_sweep = h->t;
+    if (next_sweep) *next_sweep = h->hs.t;
     return PYRO_OK;
 }
 
@@ -425,13 +708,25 @@ int pyro_sw_set_timing(pyro_sw *h, int kernel_mask)
 {
     int rc = usable(h);
     if (rc) return rc;
-    rc = collect_timing(h);
-    if (rc) return rc;
-    h->timing = kernel_mask;
-    for (int k = 0; k < kNumKernels; ++k) {
-        h->ms[k] = 0.0;
-        h->launches[k] = 0;
+    h->timer.stream = h->stream;
+    HIP_OR_FAIL(&h->broken, h->timer.collect());
+    h->timer.reset(kernel_mask);
+    return PYRO_OK;
+}
+
+static int report_times(Timer &tm, bool *broken, const char **names, int64_t *launches, double *ms, int cap,
+                        int *n_out)
+{
+    if (!n_out || cap < 0) return fail(PYRO_EINVAL, "bad output arguments");
+    HIP_OR_FAIL(broken, tm.collect());
+    int n = 0;
+    for (int k = 0; k < kNumKernels && n < cap; ++k) {
+        if (names) names[n] = kernel_name(k);
+        if (launches) launches[n] = tm.launches[k];
+        if (ms) ms[n] = tm.ms[k];
+        ++n;
     }
+    *n_out = n;
     return PYRO_OK;
 }
 
@@ -439,18 +734,7 @@ int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, doub
 {
     int rc = usable(h);
     if (rc) return rc;
-    if (!n_out || cap < 0) return fail(PYRO_EINVAL, "bad output arguments");
-    rc = collect_timing(h);
-    if (rc) return rc;
-    int n = 0;
-    for (int k = 0; k < kNumKernels && n < cap; ++k) {
-        if (names) names[n] = kernel_name(k);
-        if (launches) launches[n] = h->launches[k];
-        if (ms) ms[n] = h->ms[k];
-        ++n;
-    }
-    *n_out = n;
-    return PYRO_OK;
+    return report_times(h->timer, &h->broken, names, launches, ms, cap, n_out);
 }
 
 int pyro_sw_destroy(pyro_sw *h)
@@ -458,17 +742,285 @@ int pyro_sw_destroy(pyro_sw *h)
     if (!h) return PYRO_OK;
     int rc = PYRO_OK;
     if (h->stream && hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(PYRO_EDEVICE, "synchronize failed");
-    for (auto &tl : h->inflight) {
-        hipEventDestroy(tl.e0);
-        hipEventDestroy(tl.e1);
-    }
-    for (auto e : h->pool) hipEventDestroy(e);
+    h->timer.release();
+    if (h->solo_exec) hipGraphExecDestroy(h->solo_exec);
     if (h->own_mem) {
         hipFree(h->spins);
         hipFree(h->work);
     }
     if (h->own_stream) hipStreamDestroy(h->stream);
     delete h;
+    return rc;
+}
+
+// ------------------------------------------------------------------ groups --
+
+int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, void *stream)
+{
+    if (!out) return fail(PYRO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !members) return fail(PYRO_EINVAL, "a group needs at least one member");
+    for (int i = 0; i < n; ++i) {
+        int rc = usable(members[i]);
+        if (rc) return rc;
+        for (int j = 0; j < i; ++j)
+            if (members[j] == members[i]) return fail(PYRO_EINVAL, "a lattice appears twice in the group");
+    }
+    pyro_sw_group *g = new (std::nothrow) pyro_sw_group();
+    if (!g) return fail(PYRO_ENOMEM, "host allocation failed");
+    g->members.assign(members, members + n);
+    for (int m = 0; m < 3; ++m) g->chains[m].model = m + 1;
+    for (auto *h : g->members) g->chains[h->model - 1].reps.push_back(h);
+    if (stream) {
+        g->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete g;
+            return fail(PYRO_EDEVICE, "hipStreamCreate failed");
+        }
+        g->own_stream = true;
+    }
+    std::vector<RepState *> ptrs(n);
+    for (int i = 0; i < n; ++i) ptrs[i] = g->members[i]->d_state;
+    if (hipMalloc((void **)&g->d_members, sizeof(RepState *) * n) != hipSuccess ||
+        hipMalloc((void **)&g->d_staged, sizeof(RepState) * n) != hipSuccess ||
+        hipHostMalloc((void **)&g->h_staged, sizeof(RepState) * n) != hipSuccess ||
+        hipMemcpy(g->d_members, ptrs.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        pyro_sw_group_destroy(g);
+        return fail(PYRO_ENOMEM, "group state buffers");
+    }
+    // tile shapes: autotuned results when known for this mix of lattices
+    for (auto &ct : g->chains) {
+        if (ct.reps.empty()) continue;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(ct));
+        ct.shape = it != g_tune_cache.end() ? it->second : kTile884;
+    }
+    *out = g;
+    return PYRO_OK;
+}
+
+static int group_prepare(pyro_sw_group *g)
+{
+    bool changed = g->tables_dirty || g->seen_versions.size() != g->members.size();
+    if (!changed)
+        for (size_t i = 0; i < g->members.size(); ++i)
+            if (g->seen_versions[i] != g->members[i]->param_version) changed = true;
+    if (!changed) return PYRO_OK;
+    if (g->exec) {
+        hipGraphExecDestroy(g->exec);
+        g->exec = nullptr;
+    }
+    HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+    for (auto &ct : g->chains) HIP_OR_FAIL(&g->broken, build_group_chain(ct, ct.shape));
+    g->seen_versions.clear();
+    for (auto *h : g->members) g->seen_versions.push_back(h->param_version);
+    g->tables_dirty = false;
+    return PYRO_OK;
+}
+
+// Run `reps` armed sweeps: graph replays, or timed direct launches.
+static int group_run(pyro_sw_group *g, int64_t reps)
+{
+    Timer &tm = g->timer;
+    if (tm.mask) {
+        const LaunchHook hook = hook_of(tm, g->stream);
+        for (int64_t k = 0; k < reps; ++k) {
+            for (auto &ct : g->chains) HIP_OR_FAIL(&g->broken, launch_chain_sweep(ct.chain, g->stream, hook));
+            if (tm.inflight.size() > 8192) HIP_OR_FAIL(&g->broken, tm.collect());
+        }
+        return PYRO_OK;
+    }
+    if (!g->exec) {
+        Chain cs[3];
+        int nc = 0;
+        for (auto &ct : g->chains)
+            if (ct.chain.nreps > 0) cs[nc++] = ct.chain;
+        HIP_OR_FAIL(&g->broken, capture_sweep(cs, nc, &g->exec));
+    }
+    for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(g->exec, g->stream));
+    return PYRO_OK;
+}
+
+int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_member)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (g->broken) return fail(PYRO_ESTATE, "group failed earlier");
+    if (n_sweeps < 0) return fail(PYRO_EINVAL, "n_sweeps must be >= 0");
+    const int n = (int)g->members.size();
+    std::vector<int64_t> want(n);
+    for (int i = 0; i < n; ++i) {
+        want[i] = per_member ? per_member[i] : n_sweeps;
+        if (want[i] < 0) return fail(PYRO_EINVAL, "per-member sweep counts must be >= 0");
+        int rc = usable(g->members[i]);
+        if (rc) return rc;
+        if ((int64_t)g->members[i]->hs.t + want[i] > (int64_t)UINT32_MAX)
+            return fail(PYRO_EINVAL, "sweep index would exceed 2^32 - 1");
+    }
+    int rc = group_prepare(g);
+    if (rc) return rc;
+    for (;;) {
+        int64_t chunk = 0;
+        for (int i = 0; i < n; ++i) chunk = std::max(chunk, std::min<int64_t>(want[i], kRing));
+        if (chunk == 0) break;
+        for (int i = 0; i < n; ++i) {
+            pyro_sw *h = g->members[i];
+            rc = make_room(h, std::min<int64_t>(want[i], chunk));
+            if (rc) return rc;
+            if (h->stream != g->stream) HIP_OR_FAIL(&g->broken, hipStreamSynchronize(h->stream));
+        }
+        // the pinned staging buffer is reused: wait for the previous copy
+        HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+        for (int i = 0; i < n; ++i) {
+            g->h_staged[i] = g->members[i]->hs;
+            g->h_staged[i].remaining = (int32_t)std::min<int64_t>(want[i], chunk);
+        }
+        HIP_OR_FAIL(&g->broken, hipMemcpyAsync(g->d_staged, g->h_staged, sizeof(RepState) * n,
+                                               hipMemcpyHostToDevice, g->stream));
+        k_arm<<<blocks_for(n), kBlock, 0, g->stream>>>(g->d_members, g->d_staged, n);
+        HIP_OR_FAIL(&g->broken, hipGetLastError());
+        for (auto *h : g->members) h->busy++;
+        rc = group_run(g, chunk);
+        for (auto *h : g->members) h->busy--;
+        if (rc) return rc;
+        for (int i = 0; i < n; ++i) {
+            pyro_sw *h = g->members[i];
+            const int64_t k = std::min<int64_t>(want[i], chunk);
+            if (k > 0) {
+                h->hs.t += (uint32_t)k;
+                h->hs.ring_used += (int32_t)k;
+                h->hs.e_pending = h->hs.ring_used - 1;
+            }
+            h->hs.remaining = 0;
+            want[i] -= k;
+        }
+    }
+    // members' later calls on their own streams must see this work
+    bool other = false;
+    for (auto *h : g->members) other |= h->stream != g->stream;
+    if (other) HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+    return PYRO_OK;
+}
+
+int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (model < 1 || model > 3 || shape < 0 || shape >= kNumTileShapes)
+        return fail(PYRO_EINVAL, "bad model or shape");
+    g->chains[model - 1].shape = shape;
+    g->tables_dirty = true;
+    return PYRO_OK;
+}
+
+int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (g->broken) return fail(PYRO_ESTATE, "group failed earlier");
+    if (trial_sweeps < 1 || trial_sweeps > 1000) return fail(PYRO_EINVAL, "trial_sweeps must be in [1, 1000]");
+    const int n = (int)g->members.size();
+    // Save every member: spins and the mirrored sweep state (records so far
+    // are first moved to the member's host queue).
+    std::vector<void *> saved(n, nullptr);
+    std::vector<RepState> saved_hs(n);
+    std::vector<size_t> bytes(n);
+    int rc = PYRO_OK;
+    for (int i = 0; i < n && rc == PYRO_OK; ++i) {
+        pyro_sw *h = g->members[i];
+        rc = usable(h);
+        if (rc == PYRO_OK) rc = drain(h);
+        if (rc) break;
+        bytes[i] = h->model == PYRO_ISING ? (size_t)h->N : sizeof(float) * h->model * (size_t)h->N;
+        if (hipMalloc(&saved[i], bytes[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(PYRO_ENOMEM, "autotune backup");
+            break;
+        }
+        if (hipMemcpy(saved[i], h->spins, bytes[i], hipMemcpyDeviceToDevice) != hipSuccess)
+            rc = device_fail(&g->broken, hipErrorUnknown, "autotune backup copy");
+        saved_hs[i] = h->hs;
+    }
+    for (int m = 0; m < 3 && rc == PYRO_OK; ++m) {
+        ChainTables &ct = g->chains[m];
+        if (ct.reps.empty()) continue;
+        double best = 1e300;
+        int best_shape = ct.shape;
+        std::vector<int64_t> per(n, 0);
+        for (int i = 0; i < n; ++i)
+            if (g->members[i]->model == m + 1) per[i] = trial_sweeps;
+        for (int s = 0; s < kNumTileShapes && rc == PYRO_OK; ++s) {
+            ct.shape = s;
+            g->tables_dirty = true;
+            rc = pyro_sw_group_sweep(g, 0, per.data());  // builds tables and graph, warms caches
+            if (rc) break;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            hipEventCreate(&e0);
+            hipEventCreate(&e1);
+            hipEventRecord(e0, g->stream);
+            rc = pyro_sw_group_sweep(g, 0, per.data());
+            hipEventRecord(e1, g->stream);
+            hipEventSynchronize(e1);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            if (rc == PYRO_OK && ms < best) {
+                best = ms;
+                best_shape = s;
+            }
+        }
+        ct.shape = best_shape;
+        g->tables_dirty = true;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(ct)] = best_shape;
+    }
+    // Restore every member exactly, dropping the trial records.
+    hipStreamSynchronize(g->stream);
+    for (int i = 0; i < n; ++i) {
+        pyro_sw *h = g->members[i];
+        if (!saved[i]) continue;
+        hipStreamSynchronize(h->stream);
+        if (hipMemcpy(h->spins, saved[i], bytes[i], hipMemcpyDeviceToDevice) != hipSuccess && rc == PYRO_OK)
+            rc = device_fail(&g->broken, hipErrorUnknown, "autotune restore");
+        hipFree(saved[i]);
+        h->hs = saved_hs[i];
+        h->hs.ring_used = 0;
+        h->hs.e_pending = -1;
+    }
+    if (shapes_out)
+        for (int m = 0; m < 3; ++m) shapes_out[m] = g->chains[m].shape;
+    return rc;
+}
+
+int pyro_sw_group_set_timing(pyro_sw_group *g, int kernel_mask)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    g->timer.stream = g->stream;
+    HIP_OR_FAIL(&g->broken, g->timer.collect());
+    g->timer.reset(kernel_mask);
+    return PYRO_OK;
+}
+
+int pyro_sw_group_kernel_times(pyro_sw_group *g, const char **names, int64_t *launches, double *ms, int cap,
+                               int *n_out)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    return report_times(g->timer, &g->broken, names, launches, ms, cap, n_out);
+}
+
+int pyro_sw_group_destroy(pyro_sw_group *g)
+{
+    if (!g) return PYRO_OK;
+    int rc = PYRO_OK;
+    if (g->stream && hipStreamSynchronize(g->stream) != hipSuccess) rc = fail(PYRO_EDEVICE, "synchronize failed");
+    g->timer.release();
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    for (auto &ct : g->chains) free_tables(ct);
+    hipFree(g->d_members);
+    hipFree(g->d_staged);
+    if (g->h_staged) hipHostFree(g->h_staged);
+    if (g->own_stream) hipStreamDestroy(g->stream);
+    delete g;
     return rc;
 }
 

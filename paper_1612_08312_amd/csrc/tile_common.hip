@@ -1,0 +1,92 @@
+// Model-independent launchers of the tiled sweep: the merge of tile-crossing
+// bonds, the flip coins, the label compression used when the host reads
+// labels, and the dispatch of one sweep of a chain to its model.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "philox.hpp"
+#include "tile_common.hpp"
+
+namespace pyro {
+
+// 128 flip coins per Philox call: call g of a replica writes coin words
+// 4g .. 4g+3, so the coin of the cluster rooted at site r is bit (r mod 32)
+// of word r/32, i.e. bit (r mod 32) of word ((r/32) mod 4) of FLIP(r/128).
+__global__ __launch_bounds__(kBlock) void k_coins(Chain c)
+{
+    const int rep = c.coin_rep[blockIdx.x];
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int64_t g = (int64_t)(blockIdx.x - d.coin_base) * kBlock + threadIdx.x;
+    const int64_t ncalls = (d.N + 127) / 128;
+    if (g >= ncalls) return;
+    reinterpret_cast<uint4 *>(d.coins)[g] = philox4x32_10((uint32_t)g, st.t, kStreamFlip, 0u, d.key);
+}
+
+__global__ __launch_bounds__(kBlock) void k_compress_labels(int32_t *label, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    label[i] = uf_find(label, label[i]);
+}
+
+struct MergeLaunch {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
+    {
+        PYRO_LAUNCH(kKMerge, (k_merge<TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        PYRO_LAUNCH(kKCompress, (k_compress_roots<TX, TY, TZ>), c.ncell_blocks, kBlock, c);
+        return hipSuccess;
+    }
+};
+
+hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    return with_tile_shape<MergeLaunch>(c.shape, c, st, hook);
+}
+
+hipError_t launch_coins(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    PYRO_LAUNCH(kKCoins, k_coins, c.ncoin_blocks, kBlock, c);
+    return hipSuccess;
+}
+
+hipError_t launch_chain_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    if (c.nreps == 0) return hipSuccess;
+    return c.model == 1 ? launch_ising_sweep(c, st, hook) : launch_on_sweep(c, st, hook);
+}
+
+hipError_t launch_chain_energy_tail(const Chain &c, hipStream_t st, const LaunchHook &hook)
+{
+    if (c.nreps == 0) return hipSuccess;
+    return c.model == 1 ? launch_ising_energy_tail(c, st, hook) : launch_on_energy_tail(c, st, hook);
+}
+
+hipError_t launch_compress_labels(const RepDesc &d, hipStream_t st)
+{
+    k_compress_labels<<<blocks_for(d.N), kBlock, 0, st>>>(d.label, d.N);
+    return hipGetLastError();
+}
+
+// Tiles of the smallest built shape bound the tile count of every shape.
+static int64_t max_tiles(int L)
+{
+    int64_t m = 0;
+    for (int s = 0; s < kNumTileShapes; ++s) {
+        const TileDims t = tile_dims(s);
+        m = std::max<int64_t>(m, (int64_t)((L + t.x - 1) / t.x) * ((L + t.y - 1) / t.y) * ((L + t.z - 1) / t.z));
+    }
+    return m;
+}
+
+int64_t ipart_count(int L) { return max_tiles(L) + blocks_for((int64_t)L * L * L); }
+int64_t dpart_count(int L) { return max_tiles(L) + 3 * (int64_t)blocks_for((int64_t)L * L * L); }
+
+}  // namespace pyro

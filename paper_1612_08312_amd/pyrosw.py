@@ -41,8 +41,14 @@ EXPORTS = (
     "pyro_sw_init", "pyro_sw_workspace_size", "pyro_sw_init_ext", "pyro_sw_sweep",
     "pyro_sw_moments", "pyro_sw_get_spins", "pyro_sw_set_spins", "pyro_sw_get_labels",
     "pyro_sw_set_temperature", "pyro_sw_info", "pyro_sw_set_timing", "pyro_sw_kernel_times",
-    "pyro_sw_destroy", "pyro_sw_strerror", "pyro_sw_last_error",
+    "pyro_sw_destroy", "pyro_sw_strerror", "pyro_sw_last_error", "pyro_sw_set_tile_shape",
+    "pyro_sw_group_create", "pyro_sw_group_sweep", "pyro_sw_group_autotune",
+    "pyro_sw_group_set_tile_shape", "pyro_sw_group_set_timing", "pyro_sw_group_kernel_times",
+    "pyro_sw_group_destroy",
 )
+
+PYRO_TILE_8x8x4, PYRO_TILE_8x4x4, PYRO_TILE_4x4x4, PYRO_TILE_8x8x8 = 0, 1, 2, 3
+TILE_SHAPES = {0: "8x8x4", 1: "8x4x4", 2: "4x4x4", 3: "8x8x8"}
 
 
 class PyroSWError(RuntimeError):
@@ -80,6 +86,14 @@ def load_library():
     lib.pyro_sw_set_timing.argtypes = [vp, i32]
     lib.pyro_sw_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_destroy.argtypes = [vp]
+    lib.pyro_sw_set_tile_shape.argtypes = [vp, i32]
+    lib.pyro_sw_group_create.argtypes = [P(vp), P(vp), i32, vp]
+    lib.pyro_sw_group_sweep.argtypes = [vp, i64, P(i64)]
+    lib.pyro_sw_group_autotune.argtypes = [vp, i32, P(i32)]
+    lib.pyro_sw_group_set_tile_shape.argtypes = [vp, i32, i32]
+    lib.pyro_sw_group_set_timing.argtypes = [vp, i32]
+    lib.pyro_sw_group_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
+    lib.pyro_sw_group_destroy.argtypes = [vp]
     lib.pyro_sw_strerror.argtypes = [i32]
     lib.pyro_sw_strerror.restype = ctypes.c_char_p
     lib.pyro_sw_last_error.argtypes = []
@@ -190,15 +204,62 @@ def pyro_sw_set_timing(h, kernel_mask: int = -1):
     _check(load_library().pyro_sw_set_timing(h, int(kernel_mask)), "pyro_sw_set_timing")
 
 
-def pyro_sw_kernel_times(h) -> dict:
+def _kernel_times(fn, h, where) -> dict:
     cap = 32
     names = (ctypes.c_char_p * cap)()
     launches = (ctypes.c_int64 * cap)()
     ms = (ctypes.c_double * cap)()
     n = ctypes.c_int()
-    _check(load_library().pyro_sw_kernel_times(h, names, launches, ms, cap, ctypes.byref(n)),
-           "pyro_sw_kernel_times")
+    _check(fn(h, names, launches, ms, cap, ctypes.byref(n)), where)
     return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(n.value)}
+
+
+def pyro_sw_kernel_times(h) -> dict:
+    """{kernel name: (timed launches, total ms)} since the last set_timing."""
+    return _kernel_times(load_library().pyro_sw_kernel_times, h, "pyro_sw_kernel_times")
+
+
+def pyro_sw_set_tile_shape(h, shape: int):
+    _check(load_library().pyro_sw_set_tile_shape(h, int(shape)), "pyro_sw_set_tile_shape")
+
+
+def pyro_sw_group_create(handles, stream=None):
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    g = ctypes.c_void_p()
+    _check(load_library().pyro_sw_group_create(ctypes.byref(g), arr, len(handles), _stream_ptr(stream)),
+           "pyro_sw_group_create")
+    return g
+
+
+def pyro_sw_group_sweep(g, n_sweeps, per_member=None):
+    arr = None
+    if per_member is not None:
+        arr = (ctypes.c_int64 * len(per_member))(*[int(v) for v in per_member])
+    _check(load_library().pyro_sw_group_sweep(g, int(n_sweeps), arr), "pyro_sw_group_sweep")
+
+
+def pyro_sw_group_autotune(g, trial_sweeps=5):
+    out = (ctypes.c_int * 3)()
+    _check(load_library().pyro_sw_group_autotune(g, int(trial_sweeps), out), "pyro_sw_group_autotune")
+    return list(out)
+
+
+def pyro_sw_group_set_tile_shape(g, model, shape):
+    _check(load_library().pyro_sw_group_set_tile_shape(g, int(model), int(shape)), "pyro_sw_group_set_tile_shape")
+
+
+def pyro_sw_group_set_timing(g, kernel_mask: int = -1):
+    _check(load_library().pyro_sw_group_set_timing(g, int(kernel_mask)), "pyro_sw_group_set_timing")
+
+
+def pyro_sw_group_kernel_times(g) -> dict:
+    return _kernel_times(load_library().pyro_sw_group_kernel_times, g, "pyro_sw_group_kernel_times")
+
+
+def pyro_sw_group_destroy(g):
+    if g is not None and g.value:
+        _check(load_library().pyro_sw_group_destroy(g), "pyro_sw_group_destroy")
+        g.value = None
 
 
 def pyro_sw_destroy(h):
@@ -259,10 +320,45 @@ class Lattice:
             return self.spin_mem[: self.N].view(torch.int8)
         return self.spin_mem[: 4 * self.model * self.N].view(torch.float32).view(self.model, self.N)
 
+    def set_tile_shape(self, shape):
+        pyro_sw_set_tile_shape(self.h, shape)
+
     def close(self):
         if getattr(self, "h", None) is not None:
             pyro_sw_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """Lattices swept together from one captured graph per sweep (the
+    members keep their own records, spins and sweep indices)."""
+
+    def __init__(self, lattices, stream=None):
+        self.lattices = list(lattices)
+        if stream is None and self.lattices:
+            stream = self.lattices[0].stream
+        self.stream = stream
+        self.g = pyro_sw_group_create([lt.h for lt in self.lattices], stream)
+
+    def sweep(self, n, per_member=None):
+        pyro_sw_group_sweep(self.g, n, per_member)
+
+    def autotune(self, trial_sweeps=5):
+        return pyro_sw_group_autotune(self.g, trial_sweeps)
+
+    def set_tile_shape(self, model, shape):
+        pyro_sw_group_set_tile_shape(self.g, model, shape)
+
+    def close(self):
+        if getattr(self, "g", None) is not None:
+            pyro_sw_group_destroy(self.g)
+            self.g = None
 
     def __del__(self):
         try:
