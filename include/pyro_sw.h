@@ -75,8 +75,7 @@ typedef struct {
 
 /*
  * Create a simulation of one lattice.
- *   L      number of cubic cells per edge, 1 <= L <= 447 (so that N < 2^31 and
- *          3N < 2^32);
+ *   L      number of cubic cells per edge, 1 <= L <= 406 (so that N < 2^30);
  *   model  PYRO_ISING, PYRO_XY or PYRO_HEISENBERG;
  *   T      temperature in units of J/k_B, T > 0; T = +inf is accepted (no bond
  *          is ever activated);

@@ -15,7 +15,7 @@ namespace pyro {
 const char *kernel_name(int id)
 {
     static const char *names[kNumKernels] = {"init",     "local", "merge", "coins",   "flip",
-                                             "energy",   "finalize", "axis", "compress"};
+                                             "energy",   "finalize", "axis", "canon_store", "canon_min"};
     return (id >= 0 && id < kNumKernels) ? names[id] : "?";
 }
 

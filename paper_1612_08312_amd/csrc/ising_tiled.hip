@@ -10,14 +10,16 @@
 //                  write every site's tile-local root as a global site index
 //                  and record the active bonds that leave the tile.  The
 //                  parallel-bond count is the energy of the incoming state.
-//   k_merge / k_compress_roots  the tile-crossing bonds (tile_common.hpp).
+//   merge / canonical passes over the tile-crossing bonds (tile_common.hpp).
 //   k_coins        flip coins (tile_common.hip).
-//   k_flip_ising   per cell: roots of its 16 sites, flip coins, XOR flip of
-//                  the int8 spins, magnetisation of the new state.
+//   k_flip_ising   one workgroup per tile: canonical label of every site from
+//                  an LDS copy of the tile's labels, coin, XOR flip of the
+//                  int8 spins, magnetisation of the new state.
 //   k_finalize_ising  fixed-order sums of the partials into the records,
 //                  then advance the replica's state.
-// Local site order inside a tile follows the global order, so every root is
-// the smallest site index of its cluster whatever the schedule.
+// Local site order inside a tile follows the global order, so a tile-local
+// root is the smallest site index of its local component, and the canonical
+// passes make every label the smallest site index of its cluster.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,6 +39,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     constexpr int NS = 16 * NC;
     __shared__ int P[NS];
     __shared__ uint32_t SM[NC];
+    __shared__ int NBL[kNCellCodes * NC];
+    __shared__ uint32_t ENDS[24];
     __shared__ uint8_t K4[64];
     __shared__ int64_t red[16];
 
@@ -58,22 +62,33 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         constexpr K4Table k4 = make_k4();
         K4[tid] = k4.v[tid];
     }
+    if (tid < 24) ENDS[tid] = kDownEnds.v[tid];
     uint32_t m = 0;
     if (valid) m = spin_mask16(reinterpret_cast<const int4 *>(s)[cell]);
     SM[tid] = m;
     __syncthreads();
 
     uint64_t act = 0;
+    uint32_t intile = 0;
     int aligned_count = 0;
-    NbrCell nb[kNCellCodes];
     if (valid) {
+        NbrCell nb[kNCellCodes];
         ti.neighbours(x, y, z, cell, tid, nb);
         uint32_t nm[kNCellCodes];
         nm[kSelf] = m;
 #pragma unroll
-        for (int q = 1; q < kNCellCodes; ++q)
-            nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell]
-                                     : spin_mask16(reinterpret_cast<const int4 *>(s)[nb[q].gcell]);
+        for (int q = 0; q < kNCellCodes; ++q) {
+            NBL[q * NC + tid] = nb[q].lcell;
+            if (q > 0)
+                nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell]
+                                         : spin_mask16(reinterpret_cast<const int4 *>(s)[nb[q].gcell]);
+        }
+        // down bonds whose two ends lie in this tile
+#pragma unroll
+        for (int jj = 0; jj < 24; ++jj) {
+            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
+            intile |= (uint32_t)(nb[A.cell].lcell >= 0 && nb[B.cell].lcell >= 0) << jj;
+        }
         const uint32_t dm = down_mask16(m, nm[kMx], nm[kMy], nm[kMz], nm[kMyMz], nm[kMxMz], nm[kMxMy]);
         const uint64_t al = aligned48(m, dm);
         aligned_count = (int)__popcll(al);
@@ -88,21 +103,20 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
     }
     __syncthreads();
-    // Down tetrahedra: unite inside the tile, record the bonds that leave it.
+    // Down tetrahedra: unite inside the tile (one active bond per iteration),
+    // record the bonds that leave it.
     if (valid) {
-        uint64_t xm_bits = 0;
         const uint32_t down = (uint32_t)(act >> 24);
-#pragma unroll
-        for (int jj = 0; jj < 24; ++jj) {
-            if (!((down >> jj) & 1u)) continue;
-            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
-            const int la = nb[A.cell].lcell, lb = nb[B.cell].lcell;
-            if (la >= 0 && lb >= 0)
-                lds_unite<NC>(P, 16 * la + A.site, 16 * lb + B.site);
-            else
-                xm_bits |= 1ull << (24 + jj);
+        uint32_t todo = down & intile;
+        while (todo) {
+            const int jj = __ffs(todo) - 1;
+            todo &= todo - 1;
+            const uint32_t e = ENDS[jj];
+            const int ca = e & 0xFF, sa = (e >> 8) & 0xFF, cb = (e >> 16) & 0xFF, sb = e >> 24;
+            const int la = NBL[ca * NC + tid], lb = NBL[cb * NC + tid];
+            lds_unite<NC>(P, 16 * la + sa, 16 * lb + sb);
         }
-        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = xm_bits;
+        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = (uint64_t)(down & ~intile) << 24;
     }
     __syncthreads();
     if (valid) {
@@ -117,22 +131,30 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     if (tid == 0) d.ipart[tile] = bsum;
 }
 
-// One thread per cell: roots of its 16 sites, flips, and the magnetisation
-// of the new state.
-__global__ __launch_bounds__(kBlock) void k_flip_ising(Chain c)
+// One workgroup per tile: the labels of the tile's sites are staged in LDS,
+// so the canonical label of every site (site -> local root, both in the
+// tile) costs no scattered global read; then coins, flips and the
+// magnetisation of the new state.
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
 {
+    constexpr int NC = TX * TY * TZ;
+    __shared__ int LAB[16 * NC];
     __shared__ int64_t red[16];
-    const int rep = c.cblk_rep[blockIdx.x];
+    const int rep = c.tile_rep[blockIdx.x];
     if (c.state[rep]->remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    const int blk = blockIdx.x - d.cblk_base;
-    const int64_t cl = (int64_t)blk * kBlock + threadIdx.x;
-    const int32_t *__restrict__ label = d.label;
-    const uint32_t *__restrict__ fb = d.coins;
-    int mag = 0;
-    if (cl < d.ncell) {
-        const int4 *L4 = reinterpret_cast<const int4 *>(label + 16 * cl);
-        int lab[16];
+    const int tile = blockIdx.x - d.tile_base;
+    const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
+    const int tid = threadIdx.x;
+    const int L = d.L;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
+    const bool valid = x < L && y < L && z < L;
+    const int cell = (z * L + y) * L + x;
+    int lab[16];
+    if (valid) {
+        const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int4 v = L4[q];
@@ -141,38 +163,51 @@ __global__ __launch_bounds__(kBlock) void k_flip_ising(Chain c)
             lab[4 * q + 2] = v.z;
             lab[4 * q + 3] = v.w;
         }
-        int4 *S4 = reinterpret_cast<int4 *>(d.spins);
-        const int4 sv = S4[cl];
-        uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
-        int last_in = -1, last_root = -1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
+    }
+    __syncthreads();
+    int mag = 0;
+    if (valid) {
+        const uint32_t *__restrict__ fb = d.coins;
+        int last_in = -1, last_c = -1;
         uint32_t flipmask = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            int r = lab[k];
-            if (r != last_in) {
-                last_in = r;
-                r = uf_find(label, r);
-                last_root = r;
+            const int r0 = lab[k];  // tile-local root, or an encoded canonical label
+            int cl;
+            if (r0 < 0) {
+                cl = r0 - kCanonBase;  // the site is a merged local root
+            } else if (r0 & kTag) {
+                cl = r0 & kIdxMask;  // not produced by a complete sweep; kept in range
+            } else if (r0 == last_in) {
+                cl = last_c;
             } else {
-                r = last_root;
+                const int v = LAB[lds_pos<NC>(ti.local_key(r0))];
+                cl = v < 0 ? v - kCanonBase : (v & kIdxMask);
+                last_in = r0;
+                last_c = cl;
             }
-            flipmask |= ((fb[r >> 5] >> (r & 31)) & 1u) << k;
+            flipmask |= ((fb[cl >> 5] >> (cl & 31)) & 1u) << k;
         }
+        int4 *S4 = reinterpret_cast<int4 *>(d.spins);
+        const int4 sv = S4[cell];
+        uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
         int down = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t f4 = (flipmask >> (4 * q)) & 15u;
             // +1 (0x01) <-> -1 (0xFF) is XOR 0xFE on the flipped bytes
-            const uint32_t x = ((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
-                               ((f4 >> 3 & 1u) * 0xFE000000u);
-            w[q] ^= x;
+            const uint32_t fx = ((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
+                                ((f4 >> 3 & 1u) * 0xFE000000u);
+            w[q] ^= fx;
             down += (int)__popc(w[q] & 0x80808080u);
         }
-        S4[cl] = make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
+        S4[cell] = make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
         mag = 16 - 2 * down;
     }
     const int64_t msum = block_sum<int64_t>((int64_t)mag, red);
-    if (threadIdx.x == 0) d.ipart[d.mpart_off + blk] = msum;
+    if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
 }
 
 // Records and state: energy partials (state before this sweep) into the
@@ -185,10 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize_ising(Chain c)
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int ntiles = d.ntx * d.nty * d.ntz;
-    const int ncb = blocks_for(d.ncell);
     int64_t E = 0, M = 0;
-    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) E += d.ipart[k];
-    for (int k = threadIdx.x; k < ncb; k += blockDim.x) M += d.ipart[d.mpart_off + k];
+    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) {
+        E += d.ipart[k];
+        M += d.ipart[d.mpart_off + k];
+    }
     E = block_sum<int64_t>(E, red);
     M = block_sum<int64_t>(M, red);
     if (threadIdx.x == 0) {
@@ -242,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_ising(Chain c)
         B = 2 * (int64_t)__popcll(aligned48(m, dm)) - 48;
     }
     const int64_t bsum = block_sum<int64_t>(B, red);
-    if (threadIdx.x == 0) d.ipart[d.mpart_off + blk] = bsum;
+    if (threadIdx.x == 0) d.ipart[d.tail_off + blk] = bsum;
 }
 
 __global__ __launch_bounds__(kBlock) void k_energy_tail_finalize_ising(Chain c)
@@ -254,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_tail_finalize_ising(Chain c)
     const RepDesc &d = c.desc[rep];
     const int ncb = blocks_for(d.ncell);
     int64_t E = 0;
-    for (int k = threadIdx.x; k < ncb; k += blockDim.x) E += d.ipart[d.mpart_off + k];
+    for (int k = threadIdx.x; k < ncb; k += blockDim.x) E += d.ipart[d.tail_off + k];
     E = block_sum<int64_t>(E, red);
     if (threadIdx.x == 0) {
         d.ring[st.e_pending].bond_sum = E;
@@ -272,13 +308,22 @@ struct IsingLocal {
     }
 };
 
+struct IsingFlip {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
+    {
+        PYRO_LAUNCH(kKFlip, (k_flip_ising<TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        return hipSuccess;
+    }
+};
+
 hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
     hipError_t e = with_tile_shape<IsingLocal>(c.shape, c, st, hook);
     if (e == hipSuccess) e = launch_merge(c, st, hook);
     if (e == hipSuccess) e = launch_coins(c, st, hook);
+    if (e == hipSuccess) e = with_tile_shape<IsingFlip>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
-    PYRO_LAUNCH(kKFlip, k_flip_ising, c.ncell_blocks, kBlock, c);
     PYRO_LAUNCH(kKFinalize, k_finalize_ising, c.nreps, kBlock, c);
     return hipSuccess;
 }

@@ -51,13 +51,15 @@ struct RepDesc {
     double *dpart;     // FP64 partial sums
     float *axis;       // [4] embedding axis of the current sweep
     DevRecord *ring;   // per-sweep records
+    int *pairs;        // per-tile lists of merged local-root pairs
     // constants of the run
     uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
     float x0;                 // O(n): (float)(2J/T)
     double J;
     PhiloxKey key;
     int ring_cap;
-    int mpart_off;  // magnetisation partials start here in ipart / dpart
+    int mpart_off;  // per-tile magnetisation partials start here in ipart / dpart
+    int tail_off;   // per-cell-block partials of the energy tail start here
     // first block of this replica in each grid of its chain
     int tile_base, cblk_base, coin_base;
 };
@@ -94,6 +96,7 @@ enum KernelId : int {
     kKFinalize,
     kKAxis,
     kKCompress,
+    kKCanonMin,
     kNumKernels
 };
 const char *kernel_name(int id);
@@ -113,10 +116,16 @@ hipError_t launch_chain_sweep(const Chain &c, hipStream_t st, const LaunchHook &
 // Energy of the current state into the pending record of every replica of
 // the chain, then mark it complete.
 hipError_t launch_chain_energy_tail(const Chain &c, hipStream_t st, const LaunchHook &hook);
-// Replace every label of one replica by its final root.
-hipError_t launch_compress_labels(const RepDesc &d, hipStream_t st);
+// Canonical label (smallest site index of the cluster) of every site of one
+// replica into the device array out[N].
+hipError_t launch_canonical_labels(const RepDesc &d, int32_t *out, hipStream_t st);
 
-// Sizes of the per-replica partial-sum buffers (any tile shape).
+// Sizes of the per-replica partial-sum buffers (any tile shape):
+// ipart = [E per tile][M per tile][tail per 256-cell block],
+// dpart = [E per tile][M per tile x 3][tail per 256-cell block].
+int64_t max_tile_count(int L);
+// Ints of the per-tile pair lists of one replica (any tile shape).
+int64_t pair_list_ints(int L);
 int64_t ipart_count(int L);
 int64_t dpart_count(int L);
 

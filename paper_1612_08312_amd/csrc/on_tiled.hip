@@ -72,6 +72,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     constexpr int NC = TX * TY * TZ;
     constexpr int NS = 16 * NC;
     __shared__ int P[NS];
+    __shared__ int NBL[kNCellCodes * NC];
+    __shared__ uint32_t ENDS[24];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
 
@@ -94,15 +96,24 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
         constexpr K4Table k4 = make_k4();
         K4[tid] = k4.v[tid];
     }
+    if (tid < 24) ENDS[tid] = kDownEnds.v[tid];
 
     uint64_t act = 0;
+    uint32_t intile = 0;
     double esum = 0.0;
-    NbrCell nb[kNCellCodes];
     if (valid) {
+        NbrCell nb[kNCellCodes];
         float r[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
         ti.neighbours(x, y, z, cell, tid, nb);
+#pragma unroll
+        for (int q = 0; q < kNCellCodes; ++q) NBL[q * NC + tid] = nb[q].lcell;
+#pragma unroll
+        for (int jj = 0; jj < 24; ++jj) {
+            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
+            intile |= (uint32_t)(nb[A.cell].lcell >= 0 && nb[B.cell].lcell >= 0) << jj;
+        }
         float own[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -178,19 +189,17 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     }
     __syncthreads();
     if (valid) {
-        uint64_t xm_bits = 0;
         const uint32_t down = (uint32_t)(act >> 24);
-#pragma unroll
-        for (int jj = 0; jj < 24; ++jj) {
-            if (!((down >> jj) & 1u)) continue;
-            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
-            const int la = nb[A.cell].lcell, lb = nb[B.cell].lcell;
-            if (la >= 0 && lb >= 0)
-                lds_unite<NC>(P, 16 * la + A.site, 16 * lb + B.site);
-            else
-                xm_bits |= 1ull << (24 + jj);
+        uint32_t todo = down & intile;
+        while (todo) {
+            const int jj = __ffs(todo) - 1;
+            todo &= todo - 1;
+            const uint32_t e = ENDS[jj];
+            const int ca = e & 0xFF, sa = (e >> 8) & 0xFF, cb = (e >> 16) & 0xFF, sb = e >> 24;
+            const int la = NBL[ca * NC + tid], lb = NBL[cb * NC + tid];
+            lds_unite<NC>(P, 16 * la + sa, 16 * lb + sb);
         }
-        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = xm_bits;
+        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = (uint64_t)(down & ~intile) << 24;
     }
     __syncthreads();
     if (valid) {
@@ -205,30 +214,30 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     if (tid == 0) d.dpart[tile] = b;
 }
 
-// One thread per cell: roots, coins, reflections, FP64 magnetisation.
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_flip_on(Chain c)
+// One workgroup per tile: canonical labels from an LDS copy of the tile's
+// labels (as in the Ising flip), coins, reflections, FP64 magnetisation.
+template <int NV, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
 {
+    constexpr int NC = TX * TY * TZ;
+    __shared__ int LAB[16 * NC];
     __shared__ double red[16];
-    const int rep = c.cblk_rep[blockIdx.x];
+    const int rep = c.tile_rep[blockIdx.x];
     if (c.state[rep]->remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    const int blk = blockIdx.x - d.cblk_base;
-    const int ncb = blocks_for(d.ncell);
-    const int64_t cl = (int64_t)blk * kBlock + threadIdx.x;
+    const int tile = blockIdx.x - d.tile_base;
+    const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
+    const int tid = threadIdx.x;
+    const int L = d.L;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
+    const bool valid = x < L && y < L && z < L;
+    const int cell = (z * L + y) * L + x;
     const int64_t N = d.N;
     float *s = (float *)d.spins;
-    const int32_t *__restrict__ label = d.label;
-    const uint32_t *__restrict__ fb = d.coins;
-    double M[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) M[k] = 0.0;
-    if (cl < d.ncell) {
-        float r[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
-        const int4 *L4 = reinterpret_cast<const int4 *>(label + 16 * cl);
-        int lab[16];
+    int lab[16];
+    if (valid) {
+        const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int4 v = L4[q];
@@ -237,24 +246,42 @@ __global__ __launch_bounds__(kBlock) void k_flip_on(Chain c)
             lab[4 * q + 2] = v.z;
             lab[4 * q + 3] = v.w;
         }
-        int last_in = -1, last_root = -1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
+    }
+    __syncthreads();
+    double M[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) M[k] = 0.0;
+    if (valid) {
+        float r[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
+        const uint32_t *__restrict__ fb = d.coins;
+        int last_in = -1, last_c = -1;
         uint32_t flipmask = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            int rt = lab[k];
-            if (rt != last_in) {
-                last_in = rt;
-                rt = uf_find(label, rt);
-                last_root = rt;
+            const int r0 = lab[k];
+            int cl;
+            if (r0 < 0) {
+                cl = r0 - kCanonBase;  // the site is a merged local root
+            } else if (r0 & kTag) {
+                cl = r0 & kIdxMask;  // not produced by a complete sweep; kept in range
+            } else if (r0 == last_in) {
+                cl = last_c;
             } else {
-                rt = last_root;
+                const int v = LAB[lds_pos<NC>(ti.local_key(r0))];
+                cl = v < 0 ? v - kCanonBase : (v & kIdxMask);
+                last_in = r0;
+                last_c = cl;
             }
-            flipmask |= ((fb[rt >> 5] >> (rt & 31)) & 1u) << k;
+            flipmask |= ((fb[cl >> 5] >> (cl & 31)) & 1u) << k;
         }
         float v[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            const float4 *S4 = reinterpret_cast<const float4 *>(s + (int64_t)k * N) + 4 * cl;
+            const float4 *S4 = reinterpret_cast<const float4 *>(s + (int64_t)k * N) + 4 * (int64_t)cell;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float4 a = S4[q];
@@ -277,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_on(Chain c)
             }
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                float4 *S4 = reinterpret_cast<float4 *>(s + (int64_t)k * N) + 4 * cl;
+                float4 *S4 = reinterpret_cast<float4 *>(s + (int64_t)k * N) + 4 * (int64_t)cell;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     S4[q] = make_float4(v[k][4 * q], v[k][4 * q + 1], v[k][4 * q + 2], v[k][4 * q + 3]);
@@ -291,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_flip_on(Chain c)
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const double b = block_sum<double>(M[k], red);
-        if (threadIdx.x == 0) d.dpart[d.mpart_off + (int64_t)k * ncb + blk] = b;
+        if (tid == 0) d.dpart[d.mpart_off * (1 + k) + tile] = b;
     }
 }
 
@@ -305,7 +332,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize_on(Chain c)
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int ntiles = d.ntx * d.nty * d.ntz;
-    const int ncb = blocks_for(d.ncell);
     double E = 0.0;
     for (int k = threadIdx.x; k < ntiles; k += blockDim.x) E += d.dpart[k];
     E = block_sum<double>(E, red);
@@ -313,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_on(Chain c)
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         double v = 0.0;
-        for (int k = threadIdx.x; k < ncb; k += blockDim.x) v += d.dpart[d.mpart_off + (int64_t)q * ncb + k];
+        for (int k = threadIdx.x; k < ntiles; k += blockDim.x) v += d.dpart[d.mpart_off * (1 + q) + k];
         M[q] = block_sum<double>(v, red);
     }
     if (threadIdx.x == 0) {
@@ -369,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_on(Chain c)
         }
     }
     const double b = block_sum<double>(esum, red);
-    if (threadIdx.x == 0) d.dpart[d.mpart_off + blk] = b;
+    if (threadIdx.x == 0) d.dpart[d.tail_off + blk] = b;
 }
 
 __global__ __launch_bounds__(kBlock) void k_energy_tail_finalize_on(Chain c)
@@ -381,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_tail_finalize_on(Chain c)
     const RepDesc &d = c.desc[rep];
     const int ncb = blocks_for(d.ncell);
     double E = 0.0;
-    for (int k = threadIdx.x; k < ncb; k += blockDim.x) E += d.dpart[d.mpart_off + k];
+    for (int k = threadIdx.x; k < ncb; k += blockDim.x) E += d.dpart[d.tail_off + k];
     E = block_sum<double>(E, red);
     if (threadIdx.x == 0) {
         d.ring[st.e_pending].E = -d.J * E;
@@ -400,14 +426,24 @@ struct OnLocal {
 };
 
 template <int NV>
+struct OnFlip {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
+    {
+        PYRO_LAUNCH(kKFlip, (k_flip_on<NV, TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        return hipSuccess;
+    }
+};
+
+template <int NV>
 static hipError_t sweep_on(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
     PYRO_LAUNCH(kKAxis, k_axis, c.nreps, 64, c);
     hipError_t e = with_tile_shape<OnLocal<NV>>(c.shape, c, st, hook);
     if (e == hipSuccess) e = launch_merge(c, st, hook);
     if (e == hipSuccess) e = launch_coins(c, st, hook);
+    if (e == hipSuccess) e = with_tile_shape<OnFlip<NV>>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
-    PYRO_LAUNCH(kKFlip, k_flip_on<NV>, c.ncell_blocks, kBlock, c);
     PYRO_LAUNCH(kKFinalize, k_finalize_on<NV>, c.nreps, kBlock, c);
     return hipSuccess;
 }

@@ -60,7 +60,7 @@ int64_t coin_calls(int64_t N) { return (N + 127) / 128; }
 
 struct Layout {
     size_t spin_bytes;
-    size_t label, xmask, coins, ipart, dpart, axis, ring, state, solo_desc, solo_stp, solo_map, total;
+    size_t label, xmask, coins, ipart, dpart, axis, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
     int64_t map_len;
 };
 
@@ -83,6 +83,7 @@ Layout layout_for(int L, int model)
     ly.dpart = take(model == PYRO_ISING ? 0 : sizeof(double) * (size_t)dpart_count(L));
     ly.axis = take(4 * sizeof(float));
     ly.ring = take(sizeof(pyro_sw_record) * (size_t)kRing);
+    ly.pairs = take(sizeof(int) * (size_t)pair_list_ints(L));
     ly.state = take(sizeof(RepState));
     ly.solo_desc = take(sizeof(RepDesc));
     ly.solo_stp = take(sizeof(RepState *));
@@ -94,7 +95,7 @@ Layout layout_for(int L, int model)
 
 int check_args(int L, int model, double T, double J, int start)
 {
-    if (L < 1 || L > 447) return fail(PYRO_EINVAL, "L must be in [1, 447]");
+    if (L < 1 || L > 406) return fail(PYRO_EINVAL, "L must be in [1, 406]");
     if (model < PYRO_ISING || model > PYRO_HEISENBERG) return fail(PYRO_EINVAL, "model must be 1, 2 or 3");
     if (!(T > 0.0)) return fail(PYRO_EINVAL, "T must be > 0 (inf allowed)");
     if (!(J > 0.0) || isinf(J)) return fail(PYRO_EINVAL, "J must be finite and > 0");
@@ -287,6 +288,7 @@ RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int
     d.dpart = h->model == PYRO_ISING ? nullptr : (double *)(h->work + h->ly.dpart);
     d.axis = (float *)(h->work + h->ly.axis);
     d.ring = (DevRecord *)(h->work + h->ly.ring);
+    d.pairs = (int *)(h->work + h->ly.pairs);
     d.thr_hi = h->thr_hi;
     d.thr_lo = h->thr_lo;
     d.x0 = h->x0;
@@ -294,6 +296,7 @@ RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int
     d.key = philox_key(h->seed);
     d.ring_cap = kRing;
     d.mpart_off = (int)max_tiles(h->L);
+    d.tail_off = (int)(h->model == PYRO_ISING ? 2 * max_tiles(h->L) : 4 * max_tiles(h->L));
     d.tile_base = tile_base;
     d.cblk_base = cblk_base;
     d.coin_base = coin_base;
@@ -559,7 +562,7 @@ extern "C" {
 
 int pyro_sw_workspace_size(int L, int model, size_t *spin_bytes, size_t *work_bytes)
 {
-    if (L < 1 || L > 447) return fail(PYRO_EINVAL, "L must be in [1, 447]");
+    if (L < 1 || L > 406) return fail(PYRO_EINVAL, "L must be in [1, 406]");
     if (model < PYRO_ISING || model > PYRO_HEISENBERG) return fail(PYRO_EINVAL, "model must be 1, 2 or 3");
     const Layout ly = layout_for(L, model);
     if (spin_bytes) *spin_bytes = ly.spin_bytes;
@@ -671,9 +674,16 @@ int pyro_sw_get_labels(pyro_sw *h, int32_t *host, size_t n)
     if (rc) return rc;
     if (!host || n != (size_t)h->N) return fail(PYRO_EINVAL, "n must equal N");
     const RepDesc d = make_desc(h, h->solo_shape, 0, 0, 0);
-    HIP_OR_FAIL(&h->broken, launch_compress_labels(d, h->stream));
-    HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
-    HIP_OR_FAIL(&h->broken, hipMemcpy(host, d.label, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    int32_t *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, sizeof(int32_t) * n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PYRO_ENOMEM, "label buffer");
+    }
+    hipError_t e = launch_canonical_labels(d, tmp, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(host, tmp, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    hipFree(tmp);
+    if (e != hipSuccess) return device_fail(&h->broken, e, "get_labels");
     return PYRO_OK;
 }
 

@@ -29,19 +29,24 @@ __global__ __launch_bounds__(kBlock) void k_coins(Chain c)
     reinterpret_cast<uint4 *>(d.coins)[g] = philox4x32_10((uint32_t)g, st.t, kStreamFlip, 0u, d.key);
 }
 
-__global__ __launch_bounds__(kBlock) void k_compress_labels(int32_t *label, int64_t N)
+// Canonical label of every site into `out` (only when the host reads
+// labels; the label array itself is left as the sweep built it, so the walks
+// of other threads never see a rewritten entry).
+__global__ __launch_bounds__(kBlock) void k_canonical_labels(const int32_t *__restrict__ label,
+                                                             int32_t *__restrict__ out, int64_t N)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    label[i] = uf_find(label, label[i]);
+    out[i] = canonical_label(label, i);
 }
 
 struct MergeLaunch {
     template <int TX, int TY, int TZ>
     static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
     {
-        PYRO_LAUNCH(kKMerge, (k_merge<TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
-        PYRO_LAUNCH(kKCompress, (k_compress_roots<TX, TY, TZ>), c.ncell_blocks, kBlock, c);
+        PYRO_LAUNCH(kKMerge, (k_global<TX, TY, TZ, kPassUnite>), c.ntile_blocks, TX * TY * TZ, c);
+        PYRO_LAUNCH(kKCanonMin, (k_global<TX, TY, TZ, kPassMin>), c.ntile_blocks, TX * TY * TZ, c);
+        PYRO_LAUNCH(kKCompress, (k_global<TX, TY, TZ, kPassStore>), c.ntile_blocks, TX * TY * TZ, c);
         return hipSuccess;
     }
 };
@@ -69,9 +74,9 @@ hipError_t launch_chain_energy_tail(const Chain &c, hipStream_t st, const Launch
     return c.model == 1 ? launch_ising_energy_tail(c, st, hook) : launch_on_energy_tail(c, st, hook);
 }
 
-hipError_t launch_compress_labels(const RepDesc &d, hipStream_t st)
+hipError_t launch_canonical_labels(const RepDesc &d, int32_t *out, hipStream_t st)
 {
-    k_compress_labels<<<blocks_for(d.N), kBlock, 0, st>>>(d.label, d.N);
+    k_canonical_labels<<<blocks_for(d.N), kBlock, 0, st>>>(d.label, out, d.N);
     return hipGetLastError();
 }
 
@@ -86,7 +91,9 @@ static int64_t max_tiles(int L)
     return m;
 }
 
-int64_t ipart_count(int L) { return max_tiles(L) + blocks_for((int64_t)L * L * L); }
-int64_t dpart_count(int L) { return max_tiles(L) + 3 * (int64_t)blocks_for((int64_t)L * L * L); }
+int64_t max_tile_count(int L) { return max_tiles(L); }
+int64_t pair_list_ints(int L) { return max_tiles(L) * kPairListInts; }
+int64_t ipart_count(int L) { return 2 * max_tiles(L) + blocks_for((int64_t)L * L * L); }
+int64_t dpart_count(int L) { return 4 * max_tiles(L) + blocks_for((int64_t)L * L * L); }
 
 }  // namespace pyro

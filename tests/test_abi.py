@@ -31,7 +31,7 @@ def test_record_layout():
 
 
 @pytest.mark.parametrize("args", [
-    dict(L=0, model=1, T=4.0), dict(L=448, model=1, T=4.0), dict(L=4, model=0, T=4.0),
+    dict(L=0, model=1, T=4.0), dict(L=407, model=1, T=4.0), dict(L=4, model=0, T=4.0),
     dict(L=4, model=4, T=4.0), dict(L=4, model=1, T=0.0), dict(L=4, model=1, T=-1.0),
     dict(L=4, model=1, T=float("nan")), dict(L=4, model=1, T=4.0, J=0.0),
     dict(L=4, model=1, T=4.0, J=float("inf")), dict(L=4, model=1, T=4.0, start=2),

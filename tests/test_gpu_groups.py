@@ -1,6 +1,9 @@
 """Groups (many lattices per captured graph), tile shapes and the autotuner:
-none of them may change any result.  Every comparison here is bit-exact,
-including O(n) (same FP32 operations in the same order)."""
+none of them may change any result.  Spins, labels, magnetisations and the
+Ising energy are compared bit for bit (O(n) included: same FP32 operations
+in the same order).  The O(n) energy is an FP64 sum of per-tile partials, so
+its last bit follows the tile shape: it is compared to 1e-13 relative when
+the tiling differs."""
 import sys
 
 import numpy as np
@@ -21,10 +24,14 @@ def lat(**kw):
     return pyrosw.Lattice(**kw)
 
 
-def same_records(a, b):
+def same_records(a, b, e_rtol=0.0):
     assert len(a) == len(b)
-    for f in ("sweep", "bond_sum", "M_int", "E", "M", "m2", "m4"):
+    for f in ("sweep", "bond_sum", "M_int", "M", "m2", "m4"):
         np.testing.assert_array_equal(a[f], b[f], err_msg=f)
+    if e_rtol:
+        np.testing.assert_allclose(a["E"], b["E"], rtol=e_rtol, atol=0)
+    else:
+        np.testing.assert_array_equal(a["E"], b["E"], err_msg="E")
 
 
 MIX = [dict(L=3, model=1, T=4.2139, seed=11, start=1), dict(L=8, model=1, T=4.0, seed=12, start=1),
@@ -80,7 +87,7 @@ def test_tile_shapes_do_not_change_results(model, L):
         if ref is None:
             ref = out
         else:
-            same_records(ref[0], out[0])
+            same_records(ref[0], out[0], e_rtol=0.0 if model == 1 else 1e-13)
             np.testing.assert_array_equal(ref[1], out[1])
             np.testing.assert_array_equal(ref[2], out[2])
 
@@ -100,7 +107,7 @@ def test_autotune_changes_no_result():
     say("autotuned shapes", shapes)
     gb.sweep(13)
     for x, y in zip(a, b):
-        same_records(x.moments(), y.moments())
+        same_records(x.moments(), y.moments(), e_rtol=0.0 if x.model == 1 else 1e-13)
         np.testing.assert_array_equal(x.spins(), y.spins())
     ga.close()
     gb.close()
