@@ -29,19 +29,26 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 # Algorithmic HBM bytes per site of one launch of each Ising kernel: every
 # array element the kernel must touch, read or written once (halo re-reads,
-# root look-ups and L2/MALL hits not counted).  Tiles are 8x8x4 cells; 109 of
-# their 256 cells lie on a low face and store an 8-byte mask of the active
-# bonds that leave the tile.
-FACE_MASK_BYTES = 8.0 * 109 / 256 / 16
-BYTES_PER_SITE = {
-    "local": 1.0 + 4.0 + FACE_MASK_BYTES,  # read spins, write tile-local roots, face masks
-    "merge": FACE_MASK_BYTES,              # read face masks (label traffic is data dependent)
-    "compress": FACE_MASK_BYTES,           # read face masks
-    "coins": 1.0 / 8,                      # write one flip coin per site
-    "flip": 4.0 + 1.0 + 1.0,               # read labels, read and write spins
-    "energy": 1.0,                         # read spins
-    "finalize": 0.0,
-}
+# forest walks and L2/MALL hits not counted).  The crossing lists the local
+# kernel writes and the forest passes read are data dependent and small
+# (at most 3 pairs per down tetrahedron of a tile's low-face cells); they
+# are not counted.
+
+
+def bytes_per_site(shape):
+    del shape  # the counted traffic does not depend on the tile shape
+    return {
+        "local": 1.0 + 4.0,            # read spins, write tile-local roots
+        "unite": 0.0,                  # forest walks over the crossing lists (data dependent)
+        "canon_min": 0.0,              # idem
+        "canon_store": 0.0,            # idem
+        "coins": 1.0 / 8,              # write one flip coin per site
+        "flip": 4.0 + 1.0 + 1.0 + 1.0 / 8,  # read labels, read and write spins, read coins
+        "energy": 1.0,                 # read spins
+        "finalize": 0.0,
+    }
+
+
 SWEEP_BYTES_PER_SITE = 11.0  # whole-sweep model: read s, write/read labels, read/write s
 
 
@@ -69,7 +76,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--L", type=int, default=128)
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-sweeps", type=int, default=4, help="oracle sweeps for cpu_baseline (0: skip)")
     ap.add_argument("--tile-shape", type=int, default=-1, help="tile shape id (-1: autotune)")
     ap.add_argument("--roofline-steps", type=int, default=200,
                     help="steps of the pass that times the dominant kernel with HIP events")
@@ -98,9 +105,12 @@ def main():
     group = pyrosw.Group(lats, stream)
     if args.tile_shape >= 0:
         group.set_tile_shape(1, args.tile_shape)
+        shape = pyrosw.TILE_SHAPES[args.tile_shape]
     else:
         shapes = group.autotune(trial_sweeps=3)
-        log("bench: autotuned tile shape", pyrosw.TILE_SHAPES[shapes[0]])
+        shape = pyrosw.TILE_SHAPES[shapes[0]]
+        log("bench: autotuned tile shape", shape)
+    byte_model = bytes_per_site(shape)
 
     # Find the dominant kernel over a few timed sweeps (events on every kernel).
     pyrosw.pyro_sw_group_set_timing(group.g, -1)
@@ -137,7 +147,7 @@ def main():
     value = updates / dt
     dom_avg_s = dom_ms / max(dom_n, 1) / 1e3
     # one launch of a kernel covers all lattices of the group
-    bytes_per_launch = BYTES_PER_SITE.get(dominant, 0.0) * N * len(lats)
+    bytes_per_launch = byte_model.get(dominant, 0.0) * N * len(lats)
     achieved = bytes_per_launch / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
     binder = {}
     for T, r in zip(temps, recs):
@@ -167,6 +177,7 @@ def main():
             "start": "random",
             "sweeps_per_lattice": args.steps,
             "step": "one SW sweep of each lattice (one captured graph for all five)",
+            "tile_shape": shape,
         },
         "roofline": {
             "bound": "hbm",
@@ -176,7 +187,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "alg_bytes_per_site": BYTES_PER_SITE.get(dominant, 0.0),
+            "alg_bytes_per_site": byte_model.get(dominant, 0.0),
             "mean_launch_us": dom_avg_s * 1e6,
             "timed_launches": dom_n,
         },

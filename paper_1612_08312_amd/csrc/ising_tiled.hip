@@ -43,6 +43,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     __shared__ uint32_t ENDS[24];
     __shared__ uint8_t K4[64];
     __shared__ int64_t red[16];
+    __shared__ unsigned cursor;
 
     const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
@@ -94,39 +95,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         aligned_count = (int)__popcll(al);
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
-    // Up tetrahedra: components from the table, roots at the smallest vertex.
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
-        const int base = 16 * tid + 4 * f;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
-    }
-    __syncthreads();
-    // Down tetrahedra: unite inside the tile (one active bond per iteration),
-    // record the bonds that leave it.
-    if (valid) {
-        const uint32_t down = (uint32_t)(act >> 24);
-        uint32_t todo = down & intile;
-        while (todo) {
-            const int jj = __ffs(todo) - 1;
-            todo &= todo - 1;
-            const uint32_t e = ENDS[jj];
-            const int ca = e & 0xFF, sa = (e >> 8) & 0xFF, cb = (e >> 16) & 0xFF, sb = e >> 24;
-            const int la = NBL[ca * NC + tid], lb = NBL[cb * NC + tid];
-            lds_unite<NC>(P, 16 * la + sa, 16 * lb + sb);
-        }
-        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = (uint64_t)(down & ~intile) << 24;
-    }
-    __syncthreads();
-    if (valid) {
-        int r[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) r[k] = ti.global_site(lds_find<NC>(P, 16 * tid + k));
-        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
-    }
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, intile, P, NBL, ENDS, K4, &cursor);
     const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - 48) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }

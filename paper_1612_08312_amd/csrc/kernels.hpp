@@ -45,13 +45,13 @@ struct RepDesc {
     // device buffers owned by the replica
     void *spins;       // int8 [N] or float [n][N]
     int32_t *label;    // [N]
-    uint64_t *xmask;   // [ncell] crossing active bonds of face cells
     uint32_t *coins;   // [4 ceil(N/128)] flip coins of the current sweep
     int64_t *ipart;    // integer partial sums
     double *dpart;     // FP64 partial sums
     float *axis;       // [4] embedding axis of the current sweep
     DevRecord *ring;   // per-sweep records
-    int *pairs;        // per-tile lists of merged local-root pairs
+    int *pairs;        // per-tile crossing lists: count, pad, then (name, name) pairs
+    int list_stride;   // ints per tile list (tile shape dependent)
     // constants of the run
     uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
     float x0;                 // O(n): (float)(2J/T)
@@ -89,7 +89,7 @@ struct Chain {
 enum KernelId : int {
     kKInit = 0,
     kKLocal,
-    kKMerge,
+    kKUnite,
     kKCoins,
     kKFlip,
     kKEnergy,
@@ -124,7 +124,9 @@ hipError_t launch_canonical_labels(const RepDesc &d, int32_t *out, hipStream_t s
 // ipart = [E per tile][M per tile][tail per 256-cell block],
 // dpart = [E per tile][M per tile x 3][tail per 256-cell block].
 int64_t max_tile_count(int L);
-// Ints of the per-tile pair lists of one replica (any tile shape).
+// Ints per tile of the crossing lists for a tile shape, and ints of all
+// lists of one lattice for the shape that needs most.
+int tile_list_stride(int shape);
 int64_t pair_list_ints(int L);
 int64_t ipart_count(int L);
 int64_t dpart_count(int L);

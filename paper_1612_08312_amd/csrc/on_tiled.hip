@@ -76,6 +76,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     __shared__ uint32_t ENDS[24];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
+    __shared__ unsigned cursor;
 
     const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
@@ -180,36 +181,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
             }
         }
     }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
-        const int base = 16 * tid + 4 * f;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
-    }
-    __syncthreads();
-    if (valid) {
-        const uint32_t down = (uint32_t)(act >> 24);
-        uint32_t todo = down & intile;
-        while (todo) {
-            const int jj = __ffs(todo) - 1;
-            todo &= todo - 1;
-            const uint32_t e = ENDS[jj];
-            const int ca = e & 0xFF, sa = (e >> 8) & 0xFF, cb = (e >> 16) & 0xFF, sb = e >> 24;
-            const int la = NBL[ca * NC + tid], lb = NBL[cb * NC + tid];
-            lds_unite<NC>(P, 16 * la + sa, 16 * lb + sb);
-        }
-        if (is_face_cell(lx, ly, lz, d)) d.xmask[cell] = (uint64_t)(down & ~intile) << 24;
-    }
-    __syncthreads();
-    if (valid) {
-        int rr[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) rr[k] = ti.global_site(lds_find<NC>(P, 16 * tid + k));
-        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = make_int4(rr[4 * q], rr[4 * q + 1], rr[4 * q + 2], rr[4 * q + 3]);
-    }
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, intile, P, NBL, ENDS, K4, &cursor);
     const double b = block_sum<double>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }

@@ -60,7 +60,7 @@ int64_t coin_calls(int64_t N) { return (N + 127) / 128; }
 
 struct Layout {
     size_t spin_bytes;
-    size_t label, xmask, coins, ipart, dpart, axis, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
+    size_t label, coins, ipart, dpart, axis, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
     int64_t map_len;
 };
 
@@ -77,7 +77,6 @@ Layout layout_for(int L, int model)
         return at;
     };
     ly.label = take(sizeof(int32_t) * (size_t)N);
-    ly.xmask = take(sizeof(uint64_t) * (size_t)ncell);
     ly.coins = take(16 * (size_t)coin_calls(N));
     ly.ipart = take(sizeof(int64_t) * (size_t)ipart_count(L));
     ly.dpart = take(model == PYRO_ISING ? 0 : sizeof(double) * (size_t)dpart_count(L));
@@ -282,13 +281,13 @@ RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int
     d.N = h->N;
     d.spins = h->spins;
     d.label = (int32_t *)(h->work + h->ly.label);
-    d.xmask = (uint64_t *)(h->work + h->ly.xmask);
     d.coins = (uint32_t *)(h->work + h->ly.coins);
     d.ipart = (int64_t *)(h->work + h->ly.ipart);
     d.dpart = h->model == PYRO_ISING ? nullptr : (double *)(h->work + h->ly.dpart);
     d.axis = (float *)(h->work + h->ly.axis);
     d.ring = (DevRecord *)(h->work + h->ly.ring);
     d.pairs = (int *)(h->work + h->ly.pairs);
+    d.list_stride = tile_list_stride(shape);
     d.thr_hi = h->thr_hi;
     d.thr_lo = h->thr_lo;
     d.x0 = h->x0;

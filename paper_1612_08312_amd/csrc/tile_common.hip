@@ -40,20 +40,12 @@ __global__ __launch_bounds__(kBlock) void k_canonical_labels(const int32_t *__re
     out[i] = canonical_label(label, i);
 }
 
-struct MergeLaunch {
-    template <int TX, int TY, int TZ>
-    static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
-    {
-        PYRO_LAUNCH(kKMerge, (k_global<TX, TY, TZ, kPassUnite>), c.ntile_blocks, TX * TY * TZ, c);
-        PYRO_LAUNCH(kKCanonMin, (k_global<TX, TY, TZ, kPassMin>), c.ntile_blocks, TX * TY * TZ, c);
-        PYRO_LAUNCH(kKCompress, (k_global<TX, TY, TZ, kPassStore>), c.ntile_blocks, TX * TY * TZ, c);
-        return hipSuccess;
-    }
-};
-
 hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
-    return with_tile_shape<MergeLaunch>(c.shape, c, st, hook);
+    PYRO_LAUNCH(kKUnite, k_forest<kPassUnite>, c.ntile_blocks, kBlock, c);
+    PYRO_LAUNCH(kKCanonMin, k_forest<kPassMin>, c.ntile_blocks, kBlock, c);
+    PYRO_LAUNCH(kKCompress, k_forest<kPassStore>, c.ntile_blocks, kBlock, c);
+    return hipSuccess;
 }
 
 hipError_t launch_coins(const Chain &c, hipStream_t st, const LaunchHook &hook)
@@ -92,7 +84,26 @@ static int64_t max_tiles(int L)
 }
 
 int64_t max_tile_count(int L) { return max_tiles(L); }
-int64_t pair_list_ints(int L) { return max_tiles(L) * kPairListInts; }
+// A tile's crossing list holds at most 3 pairs for each of the 4 down
+// tetrahedra of each of its low-face cells.
+int tile_list_stride(int shape)
+{
+    const TileDims t = tile_dims(shape);
+    const int face = t.x * t.y * t.z - (t.x - 1) * (t.y - 1) * (t.z - 1);
+    return 2 + 2 * 12 * face;
+}
+
+int64_t pair_list_ints(int L)
+{
+    int64_t m = 0;
+    for (int s = 0; s < kNumTileShapes; ++s) {
+        const TileDims t = tile_dims(s);
+        const int64_t tiles = (int64_t)((L + t.x - 1) / t.x) * ((L + t.y - 1) / t.y) * ((L + t.z - 1) / t.z);
+        m = std::max(m, tiles * tile_list_stride(s));
+    }
+    return m;
+}
+
 int64_t ipart_count(int L) { return 2 * max_tiles(L) + blocks_for((int64_t)L * L * L); }
 int64_t dpart_count(int L) { return 4 * max_tiles(L) + blocks_for((int64_t)L * L * L); }
 

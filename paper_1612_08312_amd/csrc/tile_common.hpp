@@ -161,8 +161,9 @@ __device__ __forceinline__ bool is_face_cell(int lx, int ly, int lz, const RepDe
 //   kCanonBase + c      r is a merged root after the minimum pass: c is the
 //                       smallest site index of r's cluster
 // Site indices are below 2^30 (L <= 406), so the three forms are distinct and
-// the local root of any site is decodable at any time (endpoint_root), even
-// while other threads hook roots or store canonical labels.
+// the local root of any site is decodable at any time, even while other
+// threads hook roots or store canonical labels: an entry that is negative,
+// tagged or equal to the site's own index names the site itself.
 //
 // Roots are linked by a fixed pseudo-random priority (a bijective hash of
 // the site index): a root is always hooked under the root of smaller
@@ -181,23 +182,23 @@ __device__ __forceinline__ uint32_t link_priority(int x)
     return h ^ (h >> 16);
 }
 
+// Forest entries are read and written with relaxed workgroup-scope atomics,
+// which the caches may serve stale within a launch (agent-scope loads would
+// go past the per-XCD L2 on every step of every walk).  A stale value is an
+// older value of the same entry, and every value an entry ever holds is an
+// ancestor of the node in the final forest (hooks link roots, shortcuts
+// store ancestors, minimum and store passes write only encodings that end a
+// walk), so a stale walk is only longer, never wrong; the updates that
+// decide the forest (hook CAS, atomicMin) are device-wide atomics and
+// return the current value.  Launch boundaries make all writes visible.
 __device__ __forceinline__ int lab_load(const int32_t *lab, int x)
 {
-    return __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void lab_store(int32_t *lab, int x, int v)
 {
-    __hip_atomic_store(lab + x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Local root of site e.  The entry of an ordinary site never changes during
-// the global phase, and every value a local root's entry can hold decodes to
-// the site itself, so a plain (possibly stale) load is exact.
-__device__ __forceinline__ int endpoint_root(const int32_t *lab, int e)
-{
-    const int v = lab[e];
-    return (v < 0 || (v & kTag) || v == e) ? e : v;
+    __hip_atomic_store(lab + x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Root of local root x in the forest while hooking runs (shortcuts store
@@ -232,37 +233,6 @@ __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
     }
 }
 
-
-// Site `site` of the neighbour cell `code` (lattice.hpp codes) of the cell
-// at (x, y, z); xm, ym, zm are the wrapped lower coordinates.  Bit 0/1/2 of
-// the 3-bit field of a code says whether the neighbour is one cell lower in
-// x/y/z.
-__device__ __forceinline__ int nbr_site(int code, int site, int x, int y, int z, int xm, int ym, int zm, int L)
-{
-    constexpr uint32_t kLowerAxes = 0u | 1u << 3 | 2u << 6 | 4u << 9 | 6u << 12 | 5u << 15 | 3u << 18;
-    const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
-    const int cx = (mk & 1u) ? xm : x, cy = (mk & 2u) ? ym : y, cz = (mk & 4u) ? zm : z;
-    return 16 * ((cz * L + cy) * L + cx) + site;
-}
-
-// Visit the (local root, local root) pairs of the active crossing bonds owned
-// by one face cell.
-template <typename F>
-__device__ __forceinline__ void for_cross_pairs(const RepDesc &d, int cell, uint64_t m, F &&f)
-{
-    const int L = d.L;
-    const int x = cell % L, y = (cell / L) % L, z = cell / (L * L);
-    const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
-    uint32_t down = (uint32_t)(m >> 24);
-    while (down) {
-        const int jj = __ffs(down) - 1;
-        down &= down - 1;
-        const uint32_t e = kDownEnds.v[jj];
-        const int sa = nbr_site(e & 0xFF, (e >> 8) & 0xFF, x, y, z, xm, ym, zm, L);
-        const int sb = nbr_site((e >> 16) & 0xFF, e >> 24, x, y, z, xm, ym, zm, L);
-        f(endpoint_root(d.label, sa), endpoint_root(d.label, sb));
-    }
-}
 
 // Root of local root x in the merged forest (no hooking runs any more); a
 // root holds itself, or an encoded minimum once the minimum pass reached it.
@@ -301,166 +271,198 @@ __device__ __forceinline__ int canonical_label(const int32_t *label, int64_t i)
     return w < 0 ? w - kCanonBase : (w & kIdxMask);
 }
 
-enum GlobalPass : int { kPassUnite = 0, kPassMin = 1, kPassStore = 2 };
+// Site `site` of the neighbour cell `code` (lattice.hpp codes) of the cell
+// at (x, y, z); xm, ym, zm are the wrapped lower coordinates.  Bit 0/1/2 of
+// the 3-bit field of a code says whether the neighbour is one cell lower in
+// x/y/z.
+__device__ __forceinline__ int nbr_site(int code, int site, int x, int y, int z, int xm, int ym, int zm, int L)
+{
+    constexpr uint32_t kLowerAxes = 0u | 1u << 3 | 2u << 6 | 4u << 9 | 6u << 12 | 5u << 15 | 3u << 18;
+    const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
+    const int cx = (mk & 1u) ? xm : x, cy = (mk & 2u) ? ym : y, cz = (mk & 4u) ? zm : z;
+    return 16 * ((cz * L + cy) * L + cx) + site;
+}
 
-// Per-tile list of the distinct (local root, local root) pairs joined by the
-// tile's active crossing bonds, written by the unite pass for the two later
-// passes: word 0 = count (or -1 when the list overflowed; the later passes
-// then gather the pairs again), then `kPairCap` pairs (low, high).
-constexpr int kPairCap = 256;
-constexpr int kPairListInts = 1 + 2 * kPairCap;
+// Local root of site e (a plain, possibly stale load is exact: the entry of
+// an ordinary site does not change during the global phase, and any value a
+// local root's entry takes decodes to the root itself).
+__device__ __forceinline__ int endpoint_root(const int32_t *lab, int e)
+{
+    const int v = lab[e];
+    return (v < 0 || (v & kTag) || v == e) ? e : v;
+}
 
-// One workgroup per tile, three passes (three launches, each seeing the
-// previous one complete):
-//   kPassUnite  unite every distinct (root, root) pair in the global forest;
-//   kPassMin    lower each merged root to the encoding of the smallest local
-//               root of its cluster (= the smallest site of the cluster);
-//   kPassStore  store that encoding in every local root of the cluster.
-// The unite pass reads the labels of the tile's face cells and of the halo
-// cells below them into LDS with row-coalesced loads, finds the local root
-// of every crossing-bond endpoint there, and drops repeated pairs in an LDS
-// hash set (a cluster usually crosses a face through many bonds but few
-// local roots).  Items that do not fit the set are processed directly.
-template <int TX, int TY, int TZ, int PASS>
-__global__ __launch_bounds__(TX *TY *TZ) void k_global(Chain c)
+// ------------------------------------------------------ tile components ---
+// Second half of both models' tile pass (every thread of the block calls
+// it; `act` is 0 for threads without a cell): the components of the tile's
+// sites from the active bonds of its cells, written as every site's
+// tile-local root, and the tile's crossing list.
+//
+// Every site is a vertex of exactly one down tetrahedron, owned by one cell,
+// so the crossing bonds of different cells never join the same pair of
+// sites.  For each down tetrahedron with a vertex outside the tile, the
+// owning thread names each vertex by its tile-local root (inside) or its
+// site index (outside) and emits, per component of the tetrahedron's active
+// bonds, the edges from the component's smallest vertex to the others whose
+// name differs: at most 3 pairs per tetrahedron, none repeated.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
+                                                bool valid, int cell, int x, int y, int z, uint64_t act,
+                                                uint32_t intile, int *P, const int *NBL, const uint32_t *ENDS,
+                                                const uint8_t *K4, unsigned *cursor)
 {
     constexpr int NC = TX * TY * TZ;
-    constexpr int EX = TX + 1, EY = TY + 1, EZ = TZ + 1, NE = EX * EY * EZ;  // tile + low halo
-    constexpr int HASH = 1024;
-    __shared__ unsigned long long H[HASH];
-    __shared__ unsigned long long U[HASH];
-    __shared__ int n_unique;
-    __shared__ int LABS[PASS == kPassUnite ? 16 * NE : 1];
-    const int rep = c.tile_rep[blockIdx.x];
-    if (c.state[rep]->remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
-    const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
-    const int tid = threadIdx.x;
-    const int L = d.L;
-    int32_t *lab = d.label;
-    int *plist = d.pairs + (int64_t)tile * kPairListInts;
-    for (int k = tid; k < HASH; k += NC) H[k] = ~0ull;
-    if (tid == 0) n_unique = 0;
-
-    const int x0 = ti.bx * TX, y0 = ti.by * TY, z0 = ti.bz * TZ;
-    // extended-box coordinate of a neighbour coordinate (wrapped) on one axis
-    auto ext = [&](int v, int v0, int nt) { return (nt > 1 && v == (v0 == 0 ? L - 1 : v0 - 1)) ? 0 : v - v0 + 1; };
-
-    if (PASS == kPassUnite) {
-        // labels of the face layer and the halo below it (interior cells are
-        // never crossing-bond endpoints)
-        for (int e = tid; e < NE; e += NC) {
-            const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
-            if (ex > 1 && ey > 1 && ez > 1) continue;
-            int gx = x0 + ex - 1, gy = y0 + ey - 1, gz = z0 + ez - 1;
-            if (gx >= L || gy >= L || gz >= L) continue;  // beyond a ragged tile
-            if (ex == 0 && d.ntx == 1) continue;          // no halo along a single-tile axis
-            if (ey == 0 && d.nty == 1) continue;
-            if (ez == 0 && d.ntz == 1) continue;
-            if (gx < 0) gx += L;
-            if (gy < 0) gy += L;
-            if (gz < 0) gz += L;
-            const int4 *src = reinterpret_cast<const int4 *>(lab + 16 * ((gz * L + gy) * L + gx));
+    // Up tetrahedra: components from the table, roots at the smallest vertex.
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int4 v = src[q];
-                LABS[(4 * q) * NE + e] = v.x;
-                LABS[(4 * q + 1) * NE + e] = v.y;
-                LABS[(4 * q + 2) * NE + e] = v.z;
-                LABS[(4 * q + 3) * NE + e] = v.w;
-            }
+    for (int f = 0; f < 4; ++f) {
+        const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
+        const int base = 16 * tid + 4 * f;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
+    }
+    if (tid == 0) *cursor = 0;
+    __syncthreads();
+    // Down bonds with both ends in the tile (one active bond per iteration).
+    if (valid) {
+        uint32_t todo = (uint32_t)(act >> 24) & intile;
+        while (todo) {
+            const int jj = __ffs(todo) - 1;
+            todo &= todo - 1;
+            const uint32_t e = ENDS[jj];
+            const int ca = e & 0xFF, sa = (e >> 8) & 0xFF, cb = (e >> 16) & 0xFF, sb = e >> 24;
+            const int la = NBL[ca * NC + tid], lb = NBL[cb * NC + tid];
+            lds_unite<NC>(P, 16 * la + sa, 16 * lb + sb);
         }
     }
     __syncthreads();
-
-    auto process = [&](unsigned long long key) {
-        if (PASS == kPassUnite) {
-            forest_unite(lab, (int)(key >> 32), (int)(key & 0xFFFFFFFFu));
-        } else if (PASS == kPassMin) {
-            const int r = (int)key;
-            const int root = merged_root(lab, r);
-            if (lab_load(lab, root) > kCanonBase + r) atomicMin(lab + root, kCanonBase + r);
-        } else {
-            const int r = (int)key;
-            lab_store(lab, r, encoded_canon(lab, r));
-        }
-    };
-    auto insert = [&](unsigned long long key) {
-        uint32_t h = ((uint32_t)(key >> 32) * 0x9E3779B1u) ^ ((uint32_t)key * 0x85EBCA77u);
-        h ^= h >> 15;
-        for (int probe = 0; probe < 32; ++probe) {
-            const int slot = (int)((h + (uint32_t)probe) & (HASH - 1));
-            const unsigned long long prev = atomicCAS(&H[slot], ~0ull, key);
-            if (prev == ~0ull) {
-                U[atomicAdd(&n_unique, 1)] = key;
-                return;
-            }
-            if (prev == key) return;
-        }
-        process(key);  // set too crowded: no deduplication for this item
-    };
-    auto add_pair = [&](int ra, int rb) {
-        if (PASS == kPassUnite) {
-            if (ra == rb) return;
-            const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
-            insert(((unsigned long long)(unsigned)lo << 32) | (unsigned)hi);
-        } else {
-            insert((unsigned)ra);
-            if (rb != ra) insert((unsigned)rb);
-        }
-    };
-
-    // Pairs of this tile: from the list of the unite pass when it fits,
-    // otherwise from the crossing bonds themselves.
-    const int listed = PASS == kPassUnite ? -1 : plist[0];
-    if (listed >= 0) {
-        for (int k = tid; k < listed; k += NC) add_pair(plist[1 + 2 * k], plist[2 + 2 * k]);
-    } else {
-        const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (x < L && y < L && z < L && is_face_cell(lx, ly, lz, d)) {
-            const int cell = (z * L + y) * L + x;
-            const uint64_t m = d.xmask[cell];
-            if (m) {
-                if (PASS == kPassUnite) {
-                    const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
-                    uint32_t down = (uint32_t)(m >> 24);
-                    while (down) {
-                        const int jj = __ffs(down) - 1;
-                        down &= down - 1;
-                        const uint32_t e = kDownEnds.v[jj];
-                        int rts[2];
+    int2 pr[12];
+    unsigned npair = 0;
+    if (valid) {
+        int r[16];
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const uint32_t code = (e >> (16 * h)) & 0xFF, site = (e >> (16 * h + 8)) & 0xFF;
-                            constexpr uint32_t kLowerAxes =
-                                0u | 1u << 3 | 2u << 6 | 4u << 9 | 6u << 12 | 5u << 15 | 3u << 18;
-                            const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
-                            const int cx = (mk & 1u) ? xm : x, cy = (mk & 2u) ? ym : y, cz = (mk & 4u) ? zm : z;
-                            const int ecell = (ext(cz, z0, d.ntz) * EY + ext(cy, y0, d.nty)) * EX + ext(cx, x0, d.ntx);
-                            const int v = LABS[site * NE + ecell];
-                            const int gsite = 16 * ((cz * L + cy) * L + cx) + (int)site;
-                            rts[h] = (v < 0 || (v & kTag) || v == gsite) ? gsite : v;
-                        }
-                        add_pair(rts[0], rts[1]);
-                    }
-                } else {
-                    for_cross_pairs(d, cell, m, add_pair);
+        for (int k = 0; k < 16; ++k) r[k] = ti.global_site(lds_find<NC>(P, 16 * tid + k));
+        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+        const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+        if (is_face_cell(lx, ly, lz, d)) {
+            const int L = d.L;
+            const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
+            auto vertex_id = [&](int f, int mu, bool &outside) {
+                const SiteRef R = down_vertex(f, mu);
+                if (R.cell == kSelf) return r[R.site];
+                const int lc = NBL[R.cell * NC + tid];
+                if (lc >= 0) return ti.global_site(lds_find<NC>(P, 16 * lc + R.site));
+                outside = true;
+                return nbr_site(R.cell, R.site, x, y, z, xm, ym, zm, L);
+            };
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                bool outside = false;
+                const int id0 = vertex_id(f, 0, outside), id1 = vertex_id(f, 1, outside);
+                const int id2 = vertex_id(f, 2, outside), id3 = vertex_id(f, 3, outside);
+                // 0xE4: four singletons
+                const uint32_t code = outside ? K4[(uint32_t)(act >> (24 + 6 * f)) & 63u] : 0xE4u;
+#pragma unroll
+                for (int mu = 1; mu < 4; ++mu) {
+                    const int rp = (code >> (2 * mu)) & 3;
+                    const int rid = rp == 0 ? id0 : (rp == 1 ? id1 : id2);
+                    const int own = mu == 1 ? id1 : (mu == 2 ? id2 : id3);
+                    const bool emit = rp != mu && rid != own;
+                    pr[3 * f + mu - 1] = emit ? make_int2(rid, own) : make_int2(-1, -1);
+                    npair += emit;
                 }
             }
         }
     }
+    if (npair) {
+        int2 *list = reinterpret_cast<int2 *>(d.pairs + (int64_t)tile * d.list_stride) + 1;
+        unsigned at = atomicAdd(cursor, npair);
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            if (pr[k].x >= 0) list[at++] = pr[k];
+    }
     __syncthreads();
-    const int nu = n_unique;
-    if (PASS == kPassUnite && tid == 0) plist[0] = nu <= kPairCap ? nu : -1;
-    for (int k = tid; k < nu; k += NC) {
-        const unsigned long long key = U[k];
-        if (PASS == kPassUnite && nu <= kPairCap) {
-            plist[1 + 2 * k] = (int)(key >> 32);
-            plist[2 + 2 * k] = (int)(key & 0xFFFFFFFFu);
+    if (tid == 0) d.pairs[(int64_t)tile * d.list_stride] = (int)*cursor;
+}
+
+// ------------------------------------------------------- forest passes ---
+// Passes over the tiles' crossing lists, one workgroup of kBlock threads per
+// tile (three launches, each seeing the previous one complete):
+//   kPassUnite  unite the local roots of the two names of every pair;
+//   kPassMin    lower each merged root to the encoding of the smallest local
+//               root of its cluster (= the smallest site of the cluster);
+//               the workgroup first reduces per merged root in LDS, so a
+//               root shared by every pair (one giant cluster) receives one
+//               atomic per tile instead of one per pair;
+//   kPassStore  store that encoding in every local root of the list.
+enum GlobalPass : int { kPassUnite = 0, kPassMin = 1, kPassStore = 2 };
+
+template <int PASS>
+__global__ __launch_bounds__(kBlock) void k_forest(Chain c)
+{
+    constexpr int H = 1024;
+    __shared__ int HK[H];
+    __shared__ int HV[PASS == kPassMin ? H : 1];
+    const int rep = c.tile_rep[blockIdx.x];
+    if (c.state[rep]->remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int tile = blockIdx.x - d.tile_base;
+    const int *head = d.pairs + (int64_t)tile * d.list_stride;
+    const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
+    const int n = head[0];
+    const int tid = threadIdx.x;
+    int32_t *lab = d.label;
+    if (PASS == kPassUnite) {
+        for (int k = tid; k < n; k += kBlock) {
+            const int2 p = list[k];
+            forest_unite(lab, endpoint_root(lab, p.x), endpoint_root(lab, p.y));
         }
-        process(key);
+        return;
+    }
+    if (n == 0) return;
+    for (int k = tid; k < H; k += kBlock) HK[k] = -1;
+    __syncthreads();
+    // key: merged root (min pass) or local root (store pass); value: the
+    // smallest local root seen under that key (min pass)
+    auto add = [&](int key, int val) {
+        uint32_t h = (uint32_t)key * 0x9E3779B1u;
+        h ^= h >> 15;
+        for (int probe = 0; probe < 32; ++probe) {
+            const int slot = (int)((h + (uint32_t)probe) & (H - 1));
+            int prev = HK[slot];
+            if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
+            if (prev == -1 || prev == key) {
+                if (PASS == kPassMin) atomicMin(&HV[slot], val);
+                return;
+            }
+        }
+        // table full: act directly
+        if (PASS == kPassMin) {
+            if (lab_load(lab, key) > kCanonBase + val) atomicMin(lab + key, kCanonBase + val);
+        } else {
+            lab_store(lab, key, encoded_canon(lab, key));
+        }
+    };
+    if (PASS == kPassMin)
+        for (int k = tid; k < H; k += kBlock) HV[k] = INT32_MAX;
+    __syncthreads();
+    for (int k = tid; k < 2 * n; k += kBlock) {
+        const int2 p = list[k >> 1];
+        const int r = endpoint_root(lab, (k & 1) ? p.y : p.x);
+        if (PASS == kPassMin) add(merged_root(lab, r), r);
+        else add(r, r);
+    }
+    __syncthreads();
+    for (int k = tid; k < H; k += kBlock) {
+        const int key = HK[k];
+        if (key < 0) continue;
+        if (PASS == kPassMin) {
+            const int v = HV[k];
+            if (lab_load(lab, key) > kCanonBase + v) atomicMin(lab + key, kCanonBase + v);
+        } else {
+            lab_store(lab, key, encoded_canon(lab, key));
+        }
     }
 }
 
