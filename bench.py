@@ -70,6 +70,61 @@ def cpu_baseline(L, T, seed, sweeps):
                        f"random start, single-threaded C oracle, lattice build not timed")
 
 
+def batched_vs_plain(sweeps, stream, dev):
+    """The 96-replica batch (L in {8,12,16,24,32,48} x 16 temperatures in
+    [4.19, 4.24]) swept `sweeps` times as one group (one captured graph per
+    sweep, autotuned tile shape), then the same replicas one at a time, each
+    from its own captured graph on the same stream.  Records must agree
+    bit for bit."""
+    import numpy as np
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    specs = workloads.batch_replicas()
+
+    def build():
+        return [pyrosw.Lattice(L=r["L"], model=r["model"], T=r["T"], J=r["J"], seed=r["seed"],
+                               start=r["start"], device=dev, stream=stream) for r in specs]
+
+    lats = build()
+    sites = sum(lt.N for lt in lats)
+    group = pyrosw.Group(lats, stream)
+    shape = pyrosw.TILE_SHAPES[group.autotune(trial_sweeps=3)[0]]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    group.sweep(sweeps)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    rec_b = [lt.moments() for lt in lats]
+    group.close()
+    for lt in lats:
+        lt.close()
+
+    lats = build()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lt in lats:
+        lt.sweep(sweeps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    rec_p = [lt.moments() for lt in lats]
+    for lt in lats:
+        lt.close()
+    identical = all(np.array_equal(a, b) for a, b in zip(rec_b, rec_p)) and all(len(a) == sweeps for a in rec_b)
+    return {
+        "workload": "ising_batch_96_replicas",
+        "replicas": len(specs),
+        "sites_per_sweep": sites,
+        "sweeps": sweeps,
+        "tile_shape": shape,
+        "batched_spin_updates_per_s": sites * sweeps / t_batched,
+        "plain_spin_updates_per_s": sites * sweeps / t_plain,
+        "speedup": t_plain / t_batched,
+        "records_identical": bool(identical),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +133,8 @@ def main():
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--cpu-sweeps", type=int, default=4, help="oracle sweeps for cpu_baseline (0: skip)")
     ap.add_argument("--tile-shape", type=int, default=-1, help="tile shape id (-1: autotune)")
+    ap.add_argument("--batch-sweeps", type=int, default=2000,
+                    help="sweeps of the 96-replica batched-vs-plain comparison (0: skip)")
     ap.add_argument("--roofline-steps", type=int, default=200,
                     help="steps of the pass that times the dominant kernel with HIP events")
     args = ap.parse_args()
@@ -195,6 +252,9 @@ def main():
         "binder_U_second_half": binder,
         "kernel_mean_us_probe": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},
     }
+    if args.batch_sweeps > 0:
+        log(f"bench: 96-replica batch, {args.batch_sweeps} sweeps, batched then plain")
+        out["batched"] = batched_vs_plain(args.batch_sweeps, stream, dev)
     if args.cpu_sweeps > 0:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(L, temps[2], seeds[2], args.cpu_sweeps)

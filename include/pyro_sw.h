@@ -152,7 +152,7 @@ int pyro_sw_set_temperature(pyro_sw *h, double T);
  * Tile shape of the cluster labeling: the lattice is cut into boxes of cells,
  * each labelled in one workgroup's local memory before the boxes are merged.
  * The shape changes speed only, never results (labels are canonical and all
- * draws are keyed by sweep and site or bond).
+ * draws are keyed by sweep and site or bond).  A new handle uses 8x8x8.
  */
 enum { PYRO_TILE_8x8x4 = 0, PYRO_TILE_8x4x4 = 1, PYRO_TILE_4x4x4 = 2, PYRO_TILE_8x8x8 = 3 };
 int pyro_sw_set_tile_shape(pyro_sw *h, int shape);

@@ -220,7 +220,7 @@ struct pyro_sw {
     int busy = 0;  // nonzero while a group sweeps this lattice
     // solo sweeps
     ChainTables solo;
-    int solo_shape = kTile884;
+    int solo_shape = kTile888;
     hipGraphExec_t solo_exec = nullptr;
     uint64_t param_version = 1, solo_version = 0;
     Timer timer;
