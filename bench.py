@@ -125,6 +125,84 @@ def batched_vs_plain(sweeps, stream, dev):
     }
 
 
+def serving_vs_plain(n_jobs, budget_gb, quantum_ms, dev):
+    """The first `n_jobs` jobs of the Poisson serving stream (20 jobs/s;
+    models, sizes, temperatures and sweep counts as drawn by
+    workloads.serving_jobs, including one Ising L=256 job) through the job
+    server, then the same jobs run plain, one at a time in arrival order.
+    Plain latencies replay the measured plain durations through a FIFO queue
+    with the same arrival times."""
+    import numpy as np
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, serving, workloads
+
+    jobs = workloads.serving_jobs(n_jobs=n_jobs)
+    srv = pyrosw.Server(hbm_budget=int(budget_gb * (1 << 30)), max_running=64, quantum_ms=quantum_ms)
+    results, summary = serving.run_stream(srv, jobs)
+    srv.close()
+
+    durations, identical, mismatches = [], True, []
+    for r in results:
+        j = r["job"]
+        lt = pyrosw.Lattice(L=j["L"], model=j["model"], T=j["T"], J=j["J"], seed=j["seed"], start=j["start"],
+                            device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lt.sweep(j["sweeps"])
+        torch.cuda.synchronize()
+        durations.append(time.perf_counter() - t0)
+        rec = lt.moments()
+        lt.close()
+        a, b = r["records"], rec
+        same = len(a) == len(b)
+        if same:
+            for f in ("sweep", "bond_sum", "M_int", "E", "m2", "m4"):
+                exact = f in ("sweep", "bond_sum", "M_int") or j["model"] == 1
+                ok = np.array_equal(a[f], b[f]) if exact else np.allclose(a[f], b[f], rtol=1e-12, atol=1e-12)
+                if not ok:
+                    bad = np.nonzero(a[f] != b[f])[0]
+                    mismatches.append(dict(job=j["job_id"], model=j["model"], L=j["L"], field=f,
+                                           first_sweep=int(bad[0]) if len(bad) else -1, n_bad=int(len(bad))))
+                same &= bool(ok)
+        else:
+            mismatches.append(dict(job=j["job_id"], lengths=[len(a), len(b)]))
+        if not same:  # which side moves: run the job plain once more
+            lt = pyrosw.Lattice(L=j["L"], model=j["model"], T=j["T"], J=j["J"], seed=j["seed"],
+                                start=j["start"], device=dev)
+            lt.sweep(j["sweeps"])
+            again = lt.moments()
+            lt.close()
+            mismatches[-1]["plain_repeat_equal"] = bool(
+                len(again) == len(b) and all(np.array_equal(again[f], b[f]) for f in ("bond_sum", "M_int", "E")))
+        identical &= bool(same)
+    t_free, lat = 0.0, []
+    for j, d in sorted(zip(jobs, durations), key=lambda p: p[0]["arrival"]):
+        start = max(j["arrival"], t_free)
+        t_free = start + d
+        lat.append(t_free - j["arrival"])
+    updates = summary["spin_updates"]
+    return {
+        "workload": "poisson_20_jobs_per_s_mixed_models",
+        "jobs": len(jobs),
+        "models": {m: sum(1 for j in jobs if j["model"] == m) for m in (1, 2, 3)},
+        "largest_L": max(j["L"] for j in jobs),
+        "spin_updates": updates,
+        "hbm_budget_gb": budget_gb,
+        "quantum_ms": quantum_ms,
+        "served_p50_latency_s": summary["p50_latency_s"],
+        "served_p99_latency_s": summary["p99_latency_s"],
+        "served_spin_updates_per_s": summary["spin_updates_per_s"],
+        "served_makespan_s": summary["makespan_s"],
+        "plain_p50_latency_s": serving.percentile_nearest_rank(lat, 50),
+        "plain_p99_latency_s": serving.percentile_nearest_rank(lat, 99),
+        "plain_spin_updates_per_s": updates / sum(durations),
+        "plain_makespan_s": t_free,
+        "records_identical": bool(identical),
+        "mismatches": mismatches[:20],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +213,10 @@ def main():
     ap.add_argument("--tile-shape", type=int, default=-1, help="tile shape id (-1: autotune)")
     ap.add_argument("--batch-sweeps", type=int, default=2000,
                     help="sweeps of the 96-replica batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=16,
+                    help="jobs of the Poisson serving stream for the served-vs-plain comparison (0: skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the job server")
+    ap.add_argument("--serve-quantum-ms", type=float, default=20.0, help="lane quantum of the job server")
     ap.add_argument("--roofline-steps", type=int, default=200,
                     help="steps of the pass that times the dominant kernel with HIP events")
     args = ap.parse_args()
@@ -255,6 +337,9 @@ def main():
     if args.batch_sweeps > 0:
         log(f"bench: 96-replica batch, {args.batch_sweeps} sweeps, batched then plain")
         out["batched"] = batched_vs_plain(args.batch_sweeps, stream, dev)
+    if args.serve_jobs > 0:
+        log(f"bench: serving {args.serve_jobs} jobs, then the same jobs plain")
+        out["serving"] = serving_vs_plain(args.serve_jobs, args.serve_budget_gb, args.serve_quantum_ms, dev)
     if args.cpu_sweeps > 0:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(L, temps[2], seeds[2], args.cpu_sweeps)

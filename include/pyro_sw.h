@@ -211,6 +211,87 @@ int pyro_sw_group_kernel_times(pyro_sw_group *g, const char **names, int64_t *la
                                int cap, int *n_out);
 int pyro_sw_group_destroy(pyro_sw_group *g);
 
+/*
+ * Serving: a job server for a stream of independent simulation jobs, each
+ * the problem the paper states (model n, lattice size L, temperature T in
+ * units of J, number of Monte Carlo sweeps; Sec. 2), plus seed and start.
+ *
+ * The server owns one device allocation of hbm_budget bytes.  A job's
+ * footprint is its spin and workspace bytes (pyro_sw_workspace_size,
+ * rounded up to 256); jobs are admitted in arrival order while their
+ * footprint fits the free budget and fewer than max_running jobs run.  A
+ * queued job that does not fit lets later jobs pass until it has waited
+ * starve_ms; from then on no job is admitted before it.  Admitted jobs keep
+ * spins, sweep index and records resident until they finish.
+ *
+ * Running jobs are swept in lanes by lattice size (L <= 16, <= 40, <= 72,
+ * <= 136, larger): each lane is one group (pyro_sw_group_*) on its own
+ * stream, advanced a quantum at a time, the quantum being as many group
+ * sweeps as fit in quantum_ms by the lane's measured sweep time (each member
+ * runs at most its remaining sweeps).  Lanes overlap on the device.  Jobs
+ * join and leave a lane between its quanta, so work that arrives while
+ * other jobs run starts as soon as a slot and memory free up (continuous
+ * batching).  Every job's records and final spins are identical to a plain
+ * pyro_sw_init + pyro_sw_sweep run with the same arguments.
+ *
+ *   pyro_sw_server_create   hbm_budget >= 1 MiB, max_running >= 1,
+ *                           quantum_ms > 0, starve_ms >= 0.
+ *   pyro_sw_server_job_bytes  footprint of a job (no device needed).
+ *   pyro_sw_server_submit   validates and queues a job (sweeps 1..2^31-1;
+ *                           keep_spins != 0 keeps the final spins for
+ *                           pyro_sw_server_take); never waits for the device.
+ *                           PYRO_ENOMEM if the footprint exceeds the budget.
+ *   pyro_sw_server_step     one scheduling round: retire lanes whose quantum
+ *                           ended (finished jobs release their memory),
+ *                           admit queued jobs, start the next quantum of
+ *                           every idle lane.  If nothing changed it waits up
+ *                           to wait_ms for a quantum to end and repeats once.
+ *                           n_queued / n_running (may be NULL) receive the
+ *                           counts after the round.
+ *   pyro_sw_server_status   state and times of a job (seconds on the server
+ *                           clock, which starts at create; -1 = not yet).
+ *   pyro_sw_server_take     records (cap as in pyro_sw_moments; cap = 0
+ *                           gives the count only) and, when spins_host is
+ *                           not NULL, the final spins (spin_bytes as in
+ *                           pyro_sw_get_spins, job created with keep_spins)
+ *                           of a finished job; the job is forgotten unless
+ *                           cap = 0.  PYRO_ESTATE if the job is not done.
+ *   pyro_sw_server_clock    seconds since create.
+ *   pyro_sw_server_destroy  synchronises and frees everything (NULL no-op).
+ * A server is used from one thread at a time.
+ */
+typedef struct pyro_sw_server pyro_sw_server;
+typedef struct {
+    int model;      /* PYRO_ISING, PYRO_XY, PYRO_HEISENBERG */
+    int L;          /* 1..406 */
+    double T, J;    /* as in pyro_sw_init */
+    uint64_t seed;
+    int start;      /* PYRO_START_COLD or PYRO_START_RANDOM */
+    int keep_spins; /* nonzero: keep the final spins for pyro_sw_server_take */
+    int64_t sweeps; /* 1 .. 2^31 - 1 */
+} pyro_sw_job;
+enum { PYRO_JOB_QUEUED = 0, PYRO_JOB_RUNNING = 1, PYRO_JOB_DONE = 2 };
+typedef struct {
+    int64_t id;
+    int state;          /* PYRO_JOB_* */
+    int lane;           /* -1 while queued */
+    int64_t sweeps_done;
+    int64_t footprint;  /* bytes */
+    int error;          /* status of a job that failed on the device, else 0 */
+    int reserved;
+    double t_submit, t_admit, t_done;
+} pyro_sw_job_status;
+int pyro_sw_server_create(pyro_sw_server **out, size_t hbm_budget, int max_running, double quantum_ms,
+                          double starve_ms);
+int pyro_sw_server_job_bytes(const pyro_sw_job *job, size_t *bytes);
+int pyro_sw_server_submit(pyro_sw_server *s, const pyro_sw_job *job, int64_t *id);
+int pyro_sw_server_step(pyro_sw_server *s, double wait_ms, int *n_queued, int *n_running);
+int pyro_sw_server_status(pyro_sw_server *s, int64_t id, pyro_sw_job_status *out);
+int pyro_sw_server_take(pyro_sw_server *s, int64_t id, pyro_sw_record *out, int64_t cap, int64_t *n_out,
+                        void *spins_host, size_t spin_bytes);
+int pyro_sw_server_clock(pyro_sw_server *s, double *seconds);
+int pyro_sw_server_destroy(pyro_sw_server *s);
+
 /* Synchronise and free everything the library allocated.  NULL is a no-op. */
 int pyro_sw_destroy(pyro_sw *h);
 

@@ -17,6 +17,10 @@
 
 namespace pyro {
 
+// Store `msg` as the calling thread's last error (pyro_sw_last_error) and
+// return `status`.
+int record_error(int status, const char *msg);
+
 // Record layout written by the finalize kernels; identical to pyro_sw_record.
 struct DevRecord {
     int64_t sweep, bond_sum, M_int, reserved;

@@ -29,14 +29,18 @@ static_assert(sizeof(pyro_sw_record) == sizeof(DevRecord), "record layout");
 static_assert(sizeof(pyro_sw_record) == 80, "record size");
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int status, const std::string &msg)
+int pyro::record_error(int status, const char *msg)
 {
     g_last_error = msg;
     return status;
 }
+
+namespace {
+
+int fail(int status, const std::string &msg) { return record_error(status, msg.c_str()); }
 
 constexpr int kRing = 16384;  // device records per lattice before a forced drain
 constexpr size_t kAlign = 256;
@@ -184,13 +188,15 @@ struct Timer {
 
 // Chain tables in device memory for a list of replicas of one model.
 struct ChainTables {
-    int model = 0, shape = kTile884;
+    int model = 0, shape = kTile888;
     std::vector<pyro_sw *> reps;
     RepDesc *d_desc = nullptr;
     RepState **d_stp = nullptr;
     int *d_tile_rep = nullptr, *d_cblk_rep = nullptr, *d_coin_rep = nullptr;
     Chain chain{};
-    bool owned = true;  // tables allocated with hipMalloc (groups) or in a workspace (solo)
+    bool owned = true;       // tables in `block` (groups) or in a workspace (solo)
+    void *block = nullptr;   // stream-ordered allocation holding a group's tables
+    hipStream_t stream = nullptr;
 };
 
 // Process-wide autotuning results: (model, multiset of L) -> tile shape.
@@ -234,9 +240,10 @@ struct pyro_sw_group {
     hipGraphExec_t exec = nullptr;
     std::vector<uint64_t> seen_versions;
     bool tables_dirty = true;
+    void *state_block = nullptr;     // stream-ordered: d_members and d_staged
     RepState **d_members = nullptr;  // state pointer of every member
     RepState *d_staged = nullptr;
-    RepState *h_staged = nullptr;  // pinned
+    std::vector<RepState> h_staged;
     bool broken = false;
     Timer timer;
 };
@@ -302,25 +309,25 @@ RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int
     return d;
 }
 
+// Group tables live in one stream-ordered allocation on the group's stream,
+// so building or dropping a group never waits for other streams (plain
+// hipFree synchronises the whole device).
 void free_tables(ChainTables &ct)
 {
-    if (ct.owned) {
-        hipFree(ct.d_desc);
-        hipFree(ct.d_stp);
-        hipFree(ct.d_tile_rep);
-        hipFree(ct.d_cblk_rep);
-        hipFree(ct.d_coin_rep);
-    }
+    if (ct.owned && ct.block) hipFreeAsync(ct.block, ct.stream);
+    ct.block = nullptr;
     ct.d_desc = nullptr;
     ct.d_stp = nullptr;
     ct.d_tile_rep = ct.d_cblk_rep = ct.d_coin_rep = nullptr;
 }
 
-// Build (or rebuild) the device tables of a group chain (synchronous copies).
-hipError_t build_group_chain(ChainTables &ct, int shape)
+// Build (or rebuild) the device tables of a group chain on stream st; the
+// copies are complete when this returns.
+hipError_t build_group_chain(ChainTables &ct, int shape, hipStream_t st)
 {
     free_tables(ct);
     ct.owned = true;
+    ct.stream = st;
     ct.shape = shape;
     const int n = (int)ct.reps.size();
     ct.chain = Chain{};
@@ -344,20 +351,32 @@ hipError_t build_group_chain(ChainTables &ct, int shape)
         cb += nc;
         kb += nk;
     }
-    hipError_t e;
-    if ((e = hipMalloc((void **)&ct.d_desc, sizeof(RepDesc) * n)) != hipSuccess) return e;
-    if ((e = hipMalloc((void **)&ct.d_stp, sizeof(RepState *) * n)) != hipSuccess) return e;
-    if ((e = hipMalloc((void **)&ct.d_tile_rep, sizeof(int) * tmap.size())) != hipSuccess) return e;
-    if ((e = hipMalloc((void **)&ct.d_cblk_rep, sizeof(int) * cmap.size())) != hipSuccess) return e;
-    if ((e = hipMalloc((void **)&ct.d_coin_rep, sizeof(int) * kmap.size())) != hipSuccess) return e;
-    if ((e = hipMemcpy(ct.d_desc, desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    if ((e = hipMemcpy(ct.d_stp, stp.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    if ((e = hipMemcpy(ct.d_tile_rep, tmap.data(), sizeof(int) * tmap.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_desc = up(sizeof(RepDesc) * n), b_stp = up(sizeof(RepState *) * n);
+    const size_t b_t = up(sizeof(int) * tmap.size()), b_c = up(sizeof(int) * cmap.size());
+    const size_t b_k = up(sizeof(int) * kmap.size());
+    hipError_t e = hipMallocAsync(&ct.block, b_desc + b_stp + b_t + b_c + b_k, st);
+    if (e != hipSuccess) return e;
+    char *p = (char *)ct.block;
+    ct.d_desc = (RepDesc *)p;
+    ct.d_stp = (RepState **)(p + b_desc);
+    ct.d_tile_rep = (int *)(p + b_desc + b_stp);
+    ct.d_cblk_rep = (int *)(p + b_desc + b_stp + b_t);
+    ct.d_coin_rep = (int *)(p + b_desc + b_stp + b_t + b_c);
+    if ((e = hipMemcpyAsync(ct.d_desc, desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
         return e;
-    if ((e = hipMemcpy(ct.d_cblk_rep, cmap.data(), sizeof(int) * cmap.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpyAsync(ct.d_stp, stp.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
         return e;
-    if ((e = hipMemcpy(ct.d_coin_rep, kmap.data(), sizeof(int) * kmap.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpyAsync(ct.d_tile_rep, tmap.data(), sizeof(int) * tmap.size(), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
         return e;
+    if ((e = hipMemcpyAsync(ct.d_cblk_rep, cmap.data(), sizeof(int) * cmap.size(), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(ct.d_coin_rep, kmap.data(), sizeof(int) * kmap.size(), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;  // host vectors go out of scope
     ct.chain.desc = ct.d_desc;
     ct.chain.state = ct.d_stp;
     ct.chain.tile_rep = ct.d_tile_rep;
@@ -791,10 +810,14 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
     }
     std::vector<RepState *> ptrs(n);
     for (int i = 0; i < n; ++i) ptrs[i] = g->members[i]->d_state;
-    if (hipMalloc((void **)&g->d_members, sizeof(RepState *) * n) != hipSuccess ||
-        hipMalloc((void **)&g->d_staged, sizeof(RepState) * n) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_staged, sizeof(RepState) * n) != hipSuccess ||
-        hipMemcpy(g->d_members, ptrs.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    const size_t b_members = (sizeof(RepState *) * n + 255) & ~(size_t)255;
+    g->h_staged.resize(n);
+    if (hipMallocAsync(&g->state_block, b_members + sizeof(RepState) * n, g->stream) != hipSuccess ||
+        (g->d_members = (RepState **)g->state_block,
+         g->d_staged = (RepState *)((char *)g->state_block + b_members),
+         hipMemcpyAsync(g->d_members, ptrs.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice, g->stream)) !=
+            hipSuccess ||
+        hipStreamSynchronize(g->stream) != hipSuccess) {
         (void)hipGetLastError();
         pyro_sw_group_destroy(g);
         return fail(PYRO_ENOMEM, "group state buffers");
@@ -804,7 +827,7 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
         if (ct.reps.empty()) continue;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(ct));
-        ct.shape = it != g_tune_cache.end() ? it->second : kTile884;
+        ct.shape = it != g_tune_cache.end() ? it->second : kTile888;
     }
     *out = g;
     return PYRO_OK;
@@ -822,7 +845,7 @@ static int group_prepare(pyro_sw_group *g)
         g->exec = nullptr;
     }
     HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
-    for (auto &ct : g->chains) HIP_OR_FAIL(&g->broken, build_group_chain(ct, ct.shape));
+    for (auto &ct : g->chains) HIP_OR_FAIL(&g->broken, build_group_chain(ct, ct.shape, g->stream));
     g->seen_versions.clear();
     for (auto *h : g->members) g->seen_versions.push_back(h->param_version);
     g->tables_dirty = false;
@@ -879,13 +902,13 @@ int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_m
             if (rc) return rc;
             if (h->stream != g->stream) HIP_OR_FAIL(&g->broken, hipStreamSynchronize(h->stream));
         }
-        // the pinned staging buffer is reused: wait for the previous copy
+        // the staging buffer is reused: wait for the previous copy
         HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
         for (int i = 0; i < n; ++i) {
             g->h_staged[i] = g->members[i]->hs;
             g->h_staged[i].remaining = (int32_t)std::min<int64_t>(want[i], chunk);
         }
-        HIP_OR_FAIL(&g->broken, hipMemcpyAsync(g->d_staged, g->h_staged, sizeof(RepState) * n,
+        HIP_OR_FAIL(&g->broken, hipMemcpyAsync(g->d_staged, g->h_staged.data(), sizeof(RepState) * n,
                                                hipMemcpyHostToDevice, g->stream));
         k_arm<<<blocks_for(n), kBlock, 0, g->stream>>>(g->d_members, g->d_staged, n);
         HIP_OR_FAIL(&g->broken, hipGetLastError());
@@ -1025,9 +1048,7 @@ int pyro_sw_group_destroy(pyro_sw_group *g)
     g->timer.release();
     if (g->exec) hipGraphExecDestroy(g->exec);
     for (auto &ct : g->chains) free_tables(ct);
-    hipFree(g->d_members);
-    hipFree(g->d_staged);
-    if (g->h_staged) hipHostFree(g->h_staged);
+    if (g->state_block) hipFreeAsync(g->state_block, g->stream);
     if (g->own_stream) hipStreamDestroy(g->stream);
     delete g;
     return rc;

@@ -45,7 +45,26 @@ EXPORTS = (
     "pyro_sw_group_create", "pyro_sw_group_sweep", "pyro_sw_group_autotune",
     "pyro_sw_group_set_tile_shape", "pyro_sw_group_set_timing", "pyro_sw_group_kernel_times",
     "pyro_sw_group_destroy",
+    "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
+    "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
 )
+
+PYRO_JOB_QUEUED, PYRO_JOB_RUNNING, PYRO_JOB_DONE = 0, 1, 2
+
+
+class JobSpec(ctypes.Structure):
+    """pyro_sw_job."""
+    _fields_ = [("model", ctypes.c_int), ("L", ctypes.c_int), ("T", ctypes.c_double), ("J", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("start", ctypes.c_int), ("keep_spins", ctypes.c_int),
+                ("sweeps", ctypes.c_int64)]
+
+
+class JobStatus(ctypes.Structure):
+    """pyro_sw_job_status."""
+    _fields_ = [("id", ctypes.c_int64), ("state", ctypes.c_int), ("lane", ctypes.c_int),
+                ("sweeps_done", ctypes.c_int64), ("footprint", ctypes.c_int64), ("error", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 PYRO_TILE_8x8x4, PYRO_TILE_8x4x4, PYRO_TILE_4x4x4, PYRO_TILE_8x8x8 = 0, 1, 2, 3
 TILE_SHAPES = {0: "8x8x4", 1: "8x4x4", 2: "4x4x4", 3: "8x8x8"}
@@ -94,6 +113,14 @@ def load_library():
     lib.pyro_sw_group_set_timing.argtypes = [vp, i32]
     lib.pyro_sw_group_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_group_destroy.argtypes = [vp]
+    lib.pyro_sw_server_create.argtypes = [P(vp), sz, i32, f64, f64]
+    lib.pyro_sw_server_job_bytes.argtypes = [P(JobSpec), P(sz)]
+    lib.pyro_sw_server_submit.argtypes = [vp, P(JobSpec), P(i64)]
+    lib.pyro_sw_server_step.argtypes = [vp, f64, P(i32), P(i32)]
+    lib.pyro_sw_server_status.argtypes = [vp, i64, P(JobStatus)]
+    lib.pyro_sw_server_take.argtypes = [vp, i64, vp, i64, P(i64), vp, sz]
+    lib.pyro_sw_server_clock.argtypes = [vp, P(f64)]
+    lib.pyro_sw_server_destroy.argtypes = [vp]
     lib.pyro_sw_strerror.argtypes = [i32]
     lib.pyro_sw_strerror.restype = ctypes.c_char_p
     lib.pyro_sw_last_error.argtypes = []
@@ -359,6 +386,107 @@ class Group:
         if getattr(self, "g", None) is not None:
             pyro_sw_group_destroy(self.g)
             self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving --
+
+def _job_spec(job: dict) -> JobSpec:
+    return JobSpec(model=int(job["model"]), L=int(job["L"]), T=float(job["T"]), J=float(job.get("J", 1.0)),
+                   seed=int(job.get("seed", 1)), start=int(job.get("start", PYRO_START_RANDOM)),
+                   keep_spins=int(bool(job.get("keep_spins", False))), sweeps=int(job["sweeps"]))
+
+
+def pyro_sw_server_job_bytes(job: dict) -> int:
+    b = ctypes.c_size_t()
+    _check(load_library().pyro_sw_server_job_bytes(ctypes.byref(_job_spec(job)), ctypes.byref(b)),
+           "pyro_sw_server_job_bytes")
+    return b.value
+
+
+def pyro_sw_server_create(hbm_budget: int, max_running: int = 64, quantum_ms: float = 20.0,
+                          starve_ms: float = 2000.0):
+    s = ctypes.c_void_p()
+    _check(load_library().pyro_sw_server_create(ctypes.byref(s), int(hbm_budget), int(max_running),
+                                                float(quantum_ms), float(starve_ms)), "pyro_sw_server_create")
+    return s
+
+
+def pyro_sw_server_submit(s, job: dict) -> int:
+    jid = ctypes.c_int64()
+    _check(load_library().pyro_sw_server_submit(s, ctypes.byref(_job_spec(job)), ctypes.byref(jid)),
+           "pyro_sw_server_submit")
+    return jid.value
+
+
+def pyro_sw_server_step(s, wait_ms: float = 0.0):
+    nq, nr = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().pyro_sw_server_step(s, float(wait_ms), ctypes.byref(nq), ctypes.byref(nr)),
+           "pyro_sw_server_step")
+    return nq.value, nr.value
+
+
+def pyro_sw_server_status(s, job_id: int) -> dict:
+    st = JobStatus()
+    _check(load_library().pyro_sw_server_status(s, int(job_id), ctypes.byref(st)), "pyro_sw_server_status")
+    return {name: getattr(st, name) for name, _ in JobStatus._fields_ if name != "reserved"}
+
+
+def pyro_sw_server_take(s, job_id: int, spin_bytes: int = 0):
+    """(records, spins bytes or None) of a finished job; the job is then forgotten."""
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.pyro_sw_server_take(s, int(job_id), None, 0, ctypes.byref(n), None, 0), "pyro_sw_server_take")
+    out = np.zeros(max(n.value, 1), dtype=RECORD_DTYPE)
+    spins = np.zeros(spin_bytes, dtype=np.uint8) if spin_bytes else None
+    _check(lib.pyro_sw_server_take(s, int(job_id), out.ctypes.data, max(n.value, 1), ctypes.byref(n),
+                                   spins.ctypes.data if spins is not None else None, int(spin_bytes)),
+           "pyro_sw_server_take")
+    return out[:n.value], spins
+
+
+def pyro_sw_server_clock(s) -> float:
+    t = ctypes.c_double()
+    _check(load_library().pyro_sw_server_clock(s, ctypes.byref(t)), "pyro_sw_server_clock")
+    return t.value
+
+
+def pyro_sw_server_destroy(s):
+    if s is not None and s.value:
+        _check(load_library().pyro_sw_server_destroy(s), "pyro_sw_server_destroy")
+
+
+class Server:
+    """A job server (continuous batching over lanes of lattice groups)."""
+
+    def __init__(self, hbm_budget: int, max_running: int = 64, quantum_ms: float = 20.0,
+                 starve_ms: float = 2000.0):
+        self.s = pyro_sw_server_create(hbm_budget, max_running, quantum_ms, starve_ms)
+
+    def submit(self, job: dict) -> int:
+        return pyro_sw_server_submit(self.s, job)
+
+    def step(self, wait_ms: float = 0.0):
+        return pyro_sw_server_step(self.s, wait_ms)
+
+    def status(self, job_id: int) -> dict:
+        return pyro_sw_server_status(self.s, job_id)
+
+    def take(self, job_id: int, spin_bytes: int = 0):
+        return pyro_sw_server_take(self.s, job_id, spin_bytes)
+
+    def clock(self) -> float:
+        return pyro_sw_server_clock(self.s)
+
+    def close(self):
+        if getattr(self, "s", None) is not None:
+            pyro_sw_server_destroy(self.s)
+            self.s = None
 
     def __del__(self):
         try:

@@ -58,3 +58,33 @@ def test_null_handle_calls():
     n = ctypes.c_int64()
     assert lib.pyro_sw_moments(None, None, 0, ctypes.byref(n)) == pyrosw.PYRO_EINVAL
     assert pyrosw.pyro_sw_strerror(pyrosw.PYRO_EDEVICE) == "HIP device error"
+
+
+@pytest.mark.parametrize("args", [
+    dict(hbm_budget=1000), dict(hbm_budget=1 << 30, max_running=0),
+    dict(hbm_budget=1 << 30, quantum_ms=0.0), dict(hbm_budget=1 << 30, quantum_ms=float("nan")),
+    dict(hbm_budget=1 << 30, starve_ms=-1.0),
+])
+def test_server_create_rejects_bad_arguments_without_a_device(args):
+    with pytest.raises(pyrosw.PyroSWError) as ei:
+        pyrosw.pyro_sw_server_create(**args)
+    assert ei.value.status == pyrosw.PYRO_EINVAL
+
+
+def test_server_job_bytes():
+    s, w = pyrosw.pyro_sw_workspace_size(8, 2)
+    up = lambda v: (v + 255) // 256 * 256
+    assert pyrosw.pyro_sw_server_job_bytes(dict(model=2, L=8, T=2.0, sweeps=1)) == up(s) + up(w)
+    for bad in (dict(model=1, L=407, T=4.0, sweeps=1), dict(model=4, L=8, T=4.0, sweeps=1)):
+        with pytest.raises(pyrosw.PyroSWError):
+            pyrosw.pyro_sw_server_job_bytes(bad)
+
+
+def test_server_null_calls():
+    lib = pyrosw.load_library()
+    jid = ctypes.c_int64()
+    spec = pyrosw.JobSpec(model=1, L=4, T=4.0, J=1.0, seed=1, start=0, keep_spins=0, sweeps=10)
+    assert lib.pyro_sw_server_submit(None, ctypes.byref(spec), ctypes.byref(jid)) == pyrosw.PYRO_EINVAL
+    assert lib.pyro_sw_server_step(None, 0.0, None, None) == pyrosw.PYRO_EINVAL
+    assert lib.pyro_sw_server_destroy(None) == pyrosw.PYRO_OK
+    assert ctypes.sizeof(pyrosw.JobSpec) == 48 and ctypes.sizeof(pyrosw.JobStatus) == 64

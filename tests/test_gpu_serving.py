@@ -1,0 +1,116 @@
+"""Job server on the GPU (continuous batching): every job's records and final
+spins equal a plain run of the same job alone; the HBM budget is never
+exceeded; jobs arriving while others run are admitted and overlap them."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1612_08312_amd import pyrosw, serving  # noqa: E402
+
+
+def _alone(job):
+    lt = pyrosw.Lattice(L=job["L"], model=job["model"], T=job["T"], J=job.get("J", 1.0), seed=job["seed"],
+                        start=job["start"])
+    lt.sweep(job["sweeps"])
+    rec = lt.moments()
+    spins = np.frombuffer(lt.spins().tobytes(), dtype=np.uint8)
+    lt.close()
+    return rec, spins
+
+
+def _mixed_jobs():
+    # three lanes' worth of sizes, all three models, staggered arrivals
+    specs = [(1, 4, 4.21), (2, 8, 2.03), (3, 6, 1.32), (1, 16, 4.20), (1, 20, 4.22), (2, 12, 2.02),
+             (3, 24, 1.31), (1, 40, 4.21), (1, 8, 4.5), (2, 4, 1.5), (3, 10, 1.0), (1, 48, 4.2139)]
+    jobs = []
+    for k, (model, L, T) in enumerate(specs):
+        jobs.append(dict(arrival=0.004 * k, model=model, L=L, T=T, J=1.0, seed=500 + k,
+                         start=pyrosw.PYRO_START_RANDOM if k % 3 else pyrosw.PYRO_START_COLD,
+                         sweeps=40 + 23 * k))
+    return jobs
+
+
+def _check_same(job, rec, spins, rec0, spins0):
+    assert len(rec) == len(rec0) == job["sweeps"]
+    for f in ("sweep", "bond_sum", "M_int"):
+        assert np.array_equal(rec[f], rec0[f]), (job, f)
+    if job["model"] == pyrosw.PYRO_ISING:
+        for f in ("E", "M", "m2", "m4"):
+            assert np.array_equal(rec[f], rec0[f]), (job, f)
+        assert np.array_equal(spins, spins0)
+    else:
+        # same tile shape alone and in a lane: FP64 moments agree to rounding
+        for f in ("E", "M", "m2", "m4"):
+            np.testing.assert_allclose(rec[f], rec0[f], rtol=1e-12, atol=1e-12)
+        np.testing.assert_array_equal(spins, spins0)
+
+
+def test_server_mixed_stream_equals_alone():
+    jobs = _mixed_jobs()
+    srv = pyrosw.Server(hbm_budget=4 << 30, max_running=64, quantum_ms=2.0)
+    results, summary = serving.run_stream(srv, jobs, keep_spins=True)
+    srv.close()
+    assert summary["jobs"] == len(jobs)
+    lanes = set()
+    for r in results:
+        st = r["status"]
+        assert st["state"] == pyrosw.PYRO_JOB_DONE and st["error"] == 0
+        assert st["sweeps_done"] == r["job"]["sweeps"]
+        lanes.add(st["lane"])
+        rec0, spins0 = _alone(r["job"])
+        _check_same(r["job"], r["records"], r["spins"], rec0, spins0)
+    assert len(lanes) >= 3
+    # continuous batching: some job was admitted while another was running
+    iv = sorted((r["status"]["t_admit"], r["status"]["t_done"]) for r in results)
+    assert any(b[0] < a[1] for a, b in zip(iv, iv[1:]))
+
+
+def test_server_small_budget_queues_and_never_exceeds_it():
+    jobs = _mixed_jobs()
+    foot = [pyrosw.pyro_sw_server_job_bytes(j) for j in jobs]
+    budget = max(foot) + sorted(foot)[-2]  # at most about two large jobs at a time
+    srv = pyrosw.Server(hbm_budget=budget, max_running=3, quantum_ms=1.0, starve_ms=5.0)
+    results, _ = serving.run_stream(srv, jobs)
+    srv.close()
+    events = []
+    for r, f in zip(results, foot):
+        st = r["status"]
+        assert st["state"] == pyrosw.PYRO_JOB_DONE and st["error"] == 0
+        assert st["footprint"] == f
+        events.append((st["t_admit"], 1, f))
+        events.append((st["t_done"], 0, f))
+    used = running = peak = peak_run = 0
+    for t, kind, f in sorted(events):  # releases sort before admissions at equal times
+        used += f if kind else -f
+        running += 1 if kind else -1
+        peak = max(peak, used)
+        peak_run = max(peak_run, running)
+    assert peak <= (budget // 256) * 256
+    assert peak_run <= 3
+    # someone had to wait for memory or a slot
+    assert any(r["status"]["t_admit"] > r["status"]["t_submit"] + 1e-4 for r in results)
+    # results are still those of the job alone
+    for r in results[:4]:
+        rec0, _ = _alone(r["job"])
+        assert np.array_equal(r["records"]["bond_sum"], rec0["bond_sum"])
+        assert np.array_equal(r["records"]["M_int"], rec0["M_int"])
+
+
+def test_server_rejects_a_job_larger_than_the_budget():
+    srv = pyrosw.Server(hbm_budget=8 << 20)
+    with pytest.raises(pyrosw.PyroSWError) as ei:
+        srv.submit(dict(model=1, L=64, T=4.2, sweeps=10))
+    assert ei.value.status == pyrosw.PYRO_ENOMEM
+    jid = srv.submit(dict(model=1, L=4, T=4.2, seed=3, start=0, sweeps=25))
+    for _ in range(10000):
+        nq, nr = srv.step(1.0)
+        if nq == 0 and nr == 0:
+            break
+    rec, _ = srv.take(jid)
+    assert len(rec) == 25
+    with pytest.raises(pyrosw.PyroSWError):
+        srv.status(jid)  # taken jobs are forgotten
+    srv.close()
