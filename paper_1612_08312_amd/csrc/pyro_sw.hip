@@ -240,10 +240,7 @@ struct pyro_sw_group {
     hipGraphExec_t exec = nullptr;
     std::vector<uint64_t> seen_versions;
     bool tables_dirty = true;
-    void *state_block = nullptr;     // stream-ordered: d_members and d_staged
-    RepState **d_members = nullptr;  // state pointer of every member
-    RepState *d_staged = nullptr;
-    std::vector<RepState> h_staged;
+    RepState **d_members = nullptr;  // state pointer of every member (stream-ordered allocation)
     bool broken = false;
     Timer timer;
 };
@@ -447,11 +444,25 @@ hipError_t capture_sweep(const Chain *chains, int nchains, hipGraphExec_t *exec)
     return e;
 }
 
-// Copy staged states into the replicas' device states, in stream order.
-__global__ void k_arm(RepState *const *stp, const RepState *staged, int n)
+// Arming writes replica states in stream order.  The states travel as
+// kernel arguments, which are copied when the launch is enqueued, so no host
+// buffer has to outlive the call (an asynchronous copy from pageable host
+// memory gives no such guarantee).
+constexpr int kArmBatch = 96;  // 96 x 16 B of kernel arguments per launch
+struct ArmBatch {
+    RepState v[kArmBatch];
+};
+static_assert(sizeof(RepState) == 16, "RepState layout");
+
+__global__ void k_arm(RepState *const *stp, ArmBatch b, int first, int n)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) *stp[i] = staged[i];
+    const int i = threadIdx.x;
+    if (i < n) *stp[first + i] = b.v[i];
+}
+
+__global__ void k_arm_one(RepState *dst, RepState v)
+{
+    if (threadIdx.x == 0) *dst = v;
 }
 
 int usable(const pyro_sw *h)
@@ -614,8 +625,8 @@ int pyro_sw_sweep(pyro_sw *h, int64_t n_sweeps)
         if (h->solo_version != h->param_version) HIP_OR_FAIL(&h->broken, build_solo_chain(h));
         RepState armed = h->hs;
         armed.remaining = (int32_t)chunk;
-        HIP_OR_FAIL(&h->broken, hipMemcpyAsync(h->d_state, &armed, sizeof(RepState), hipMemcpyHostToDevice,
-                                               h->stream));
+        k_arm_one<<<1, 64, 0, h->stream>>>(h->d_state, armed);
+        HIP_OR_FAIL(&h->broken, hipGetLastError());
         if (tm.mask) {
             const LaunchHook hook = hook_of(tm, h->stream);
             for (int64_t k = 0; k < chunk; ++k) {
@@ -810,12 +821,8 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
     }
     std::vector<RepState *> ptrs(n);
     for (int i = 0; i < n; ++i) ptrs[i] = g->members[i]->d_state;
-    const size_t b_members = (sizeof(RepState *) * n + 255) & ~(size_t)255;
-    g->h_staged.resize(n);
-    if (hipMallocAsync(&g->state_block, b_members + sizeof(RepState) * n, g->stream) != hipSuccess ||
-        (g->d_members = (RepState **)g->state_block,
-         g->d_staged = (RepState *)((char *)g->state_block + b_members),
-         hipMemcpyAsync(g->d_members, ptrs.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice, g->stream)) !=
+    if (hipMallocAsync((void **)&g->d_members, sizeof(RepState *) * n, g->stream) != hipSuccess ||
+        hipMemcpyAsync(g->d_members, ptrs.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice, g->stream) !=
             hipSuccess ||
         hipStreamSynchronize(g->stream) != hipSuccess) {
         (void)hipGetLastError();
@@ -902,16 +909,16 @@ int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_m
             if (rc) return rc;
             if (h->stream != g->stream) HIP_OR_FAIL(&g->broken, hipStreamSynchronize(h->stream));
         }
-        // the staging buffer is reused: wait for the previous copy
-        HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
-        for (int i = 0; i < n; ++i) {
-            g->h_staged[i] = g->members[i]->hs;
-            g->h_staged[i].remaining = (int32_t)std::min<int64_t>(want[i], chunk);
+        for (int first = 0; first < n; first += kArmBatch) {
+            ArmBatch b{};
+            const int cnt = std::min(kArmBatch, n - first);
+            for (int i = 0; i < cnt; ++i) {
+                b.v[i] = g->members[first + i]->hs;
+                b.v[i].remaining = (int32_t)std::min<int64_t>(want[first + i], chunk);
+            }
+            k_arm<<<1, kArmBatch, 0, g->stream>>>(g->d_members, b, first, cnt);
+            HIP_OR_FAIL(&g->broken, hipGetLastError());
         }
-        HIP_OR_FAIL(&g->broken, hipMemcpyAsync(g->d_staged, g->h_staged.data(), sizeof(RepState) * n,
-                                               hipMemcpyHostToDevice, g->stream));
-        k_arm<<<blocks_for(n), kBlock, 0, g->stream>>>(g->d_members, g->d_staged, n);
-        HIP_OR_FAIL(&g->broken, hipGetLastError());
         for (auto *h : g->members) h->busy++;
         rc = group_run(g, chunk);
         for (auto *h : g->members) h->busy--;
@@ -1048,7 +1055,7 @@ int pyro_sw_group_destroy(pyro_sw_group *g)
     g->timer.release();
     if (g->exec) hipGraphExecDestroy(g->exec);
     for (auto &ct : g->chains) free_tables(ct);
-    if (g->state_block) hipFreeAsync(g->state_block, g->stream);
+    if (g->d_members) hipFreeAsync(g->d_members, g->stream);
     if (g->own_stream) hipStreamDestroy(g->stream);
     delete g;
     return rc;
