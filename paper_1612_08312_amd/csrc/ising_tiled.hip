@@ -39,8 +39,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     constexpr int NS = 16 * NC;
     __shared__ int P[NS];
     __shared__ uint32_t SM[NC];
-    __shared__ int NBL[kNCellCodes * NC];
-    __shared__ uint32_t ENDS[24];
+    __shared__ uint32_t U[kUnionsPerCell * NC];
     __shared__ uint8_t K4[64];
     __shared__ int64_t red[16];
     __shared__ unsigned cursor;
@@ -63,15 +62,16 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         constexpr K4Table k4 = make_k4();
         K4[tid] = k4.v[tid];
     }
-    if (tid < 24) ENDS[tid] = kDownEnds.v[tid];
     uint32_t m = 0;
     if (valid) m = spin_mask16(reinterpret_cast<const int4 *>(s)[cell]);
     SM[tid] = m;
     __syncthreads();
 
     uint64_t act = 0;
-    uint32_t intile = 0;
     int aligned_count = 0;
+    int lc[kNCellCodes];
+#pragma unroll
+    for (int q = 0; q < kNCellCodes; ++q) lc[q] = -1;
     if (valid) {
         NbrCell nb[kNCellCodes];
         ti.neighbours(x, y, z, cell, tid, nb);
@@ -79,23 +79,17 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         nm[kSelf] = m;
 #pragma unroll
         for (int q = 0; q < kNCellCodes; ++q) {
-            NBL[q * NC + tid] = nb[q].lcell;
+            lc[q] = nb[q].lcell;
             if (q > 0)
                 nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell]
                                          : spin_mask16(reinterpret_cast<const int4 *>(s)[nb[q].gcell]);
-        }
-        // down bonds whose two ends lie in this tile
-#pragma unroll
-        for (int jj = 0; jj < 24; ++jj) {
-            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
-            intile |= (uint32_t)(nb[A.cell].lcell >= 0 && nb[B.cell].lcell >= 0) << jj;
         }
         const uint32_t dm = down_mask16(m, nm[kMx], nm[kMy], nm[kMz], nm[kMyMz], nm[kMxMz], nm[kMxMy]);
         const uint64_t al = aligned48(m, dm);
         aligned_count = (int)__popcll(al);
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, intile, P, NBL, ENDS, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, lc, P, U, K4, &cursor);
     const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - 48) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }

@@ -72,8 +72,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     constexpr int NC = TX * TY * TZ;
     constexpr int NS = 16 * NC;
     __shared__ int P[NS];
-    __shared__ int NBL[kNCellCodes * NC];
-    __shared__ uint32_t ENDS[24];
+    __shared__ uint32_t U[kUnionsPerCell * NC];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
     __shared__ unsigned cursor;
@@ -97,11 +96,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
         constexpr K4Table k4 = make_k4();
         K4[tid] = k4.v[tid];
     }
-    if (tid < 24) ENDS[tid] = kDownEnds.v[tid];
 
     uint64_t act = 0;
-    uint32_t intile = 0;
     double esum = 0.0;
+    int lc[kNCellCodes];
+#pragma unroll
+    for (int q = 0; q < kNCellCodes; ++q) lc[q] = -1;
     if (valid) {
         NbrCell nb[kNCellCodes];
         float r[NV];
@@ -109,12 +109,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
         ti.neighbours(x, y, z, cell, tid, nb);
 #pragma unroll
-        for (int q = 0; q < kNCellCodes; ++q) NBL[q * NC + tid] = nb[q].lcell;
-#pragma unroll
-        for (int jj = 0; jj < 24; ++jj) {
-            const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
-            intile |= (uint32_t)(nb[A.cell].lcell >= 0 && nb[B.cell].lcell >= 0) << jj;
-        }
+        for (int q = 0; q < kNCellCodes; ++q) lc[q] = nb[q].lcell;
         float own[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -181,7 +176,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
             }
         }
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, intile, P, NBL, ENDS, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, lc, P, U, K4, &cursor);
     const double b = block_sum<double>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }

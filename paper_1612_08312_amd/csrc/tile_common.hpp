@@ -216,6 +216,9 @@ __device__ __forceinline__ int forest_find(int32_t *lab, int x)
     return x;
 }
 
+// Union of the trees of local roots a and b: at two roots the one of larger
+// priority is hooked under the other by CAS; a lost CAS continues from the
+// value it returned.
 __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
 {
     for (int it = 0; it < kWalkCap; ++it) {
@@ -233,7 +236,6 @@ __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
     }
 }
 
-
 // Root of local root x in the merged forest (no hooking runs any more); a
 // root holds itself, or an encoded minimum once the minimum pass reached it.
 __device__ __forceinline__ int merged_root(const int32_t *lab, int x)
@@ -247,8 +249,8 @@ __device__ __forceinline__ int merged_root(const int32_t *lab, int x)
 }
 
 // Encoded canonical index of the cluster of local root x (after the
-// minimum pass).  Only negative values are stored by the store pass, and
-// walks stop at the first negative value, so no walk can loop.
+// minimum pass): the walk stops at the first negative value, the tree
+// root's encoded minimum or one the store pass has already copied down.
 __device__ __forceinline__ int encoded_canon(const int32_t *lab, int x)
 {
     for (int it = 0; it < kWalkCap; ++it) {
@@ -261,14 +263,17 @@ __device__ __forceinline__ int encoded_canon(const int32_t *lab, int x)
 }
 
 // Canonical label (smallest site index of the cluster) of any site once the
-// store pass is done: site -> local root -> itself or its encoding.
+// store pass is done: site -> local root -> itself or its encoding (a walk
+// from a still-hooked local root is kept as a safeguard).
 __device__ __forceinline__ int canonical_label(const int32_t *label, int64_t i)
 {
     const int v = label[i];
     if (v < 0) return v - kCanonBase;
-    const int r = v & kIdxMask;
+    const int r = (v & kTag) ? (int)i : v;
     const int w = label[r];
-    return w < 0 ? w - kCanonBase : (w & kIdxMask);
+    if (w < 0) return w - kCanonBase;
+    if (w & kTag) return encoded_canon(label, r) - kCanonBase;
+    return r;
 }
 
 // Site `site` of the neighbour cell `code` (lattice.hpp codes) of the cell
@@ -292,26 +297,51 @@ __device__ __forceinline__ int endpoint_root(const int32_t *lab, int e)
     return (v < 0 || (v & kTag) || v == e) ? e : v;
 }
 
+// Local root named by a crossing-list entry: a tagged name is a local root
+// already; a site index is looked up (endpoint_root).
+__device__ __forceinline__ int name_root(const int32_t *lab, int name)
+{
+    return (name & kTag) ? (name & kIdxMask) : endpoint_root(lab, name);
+}
+
 // ------------------------------------------------------ tile components ---
+// Union-list entries per cell of a tile; unions beyond the list are done by
+// the thread that found them.
+constexpr int kUnionsPerCell = 8;
+
 // Second half of both models' tile pass (every thread of the block calls
-// it; `act` is 0 for threads without a cell): the components of the tile's
-// sites from the active bonds of its cells, written as every site's
-// tile-local root, and the tile's crossing list.
+// it; `act` is 0 for threads without a cell, lc[] holds the local index of
+// each neighbour cell of the thread's cell, or -1 outside the tile):
+// the components of the tile's sites from the active bonds of its cells,
+// written as every site's tile-local root, and the tile's crossing list.
+//
+// Inside the tile, each down tetrahedron contributes the spanning edges of
+// the components of its active bonds whose two ends lie in the tile (at most
+// 3, from the K4 table); all threads then process the tile's list of such
+// unions evenly, so one busy cell does not hold up its wave.
 //
 // Every site is a vertex of exactly one down tetrahedron, owned by one cell,
 // so the crossing bonds of different cells never join the same pair of
 // sites.  For each down tetrahedron with a vertex outside the tile, the
-// owning thread names each vertex by its tile-local root (inside) or its
-// site index (outside) and emits, per component of the tetrahedron's active
-// bonds, the edges from the component's smallest vertex to the others whose
-// name differs: at most 3 pairs per tetrahedron, none repeated.
+// owning thread names each vertex by its tile-local root with the tag bit
+// set (inside) or by its site index (outside) and emits, per component of
+// the tetrahedron's active bonds, the edges from the component's smallest
+// vertex to the others whose name differs: at most 3 pairs per tetrahedron,
+// none repeated.
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
                                                 bool valid, int cell, int x, int y, int z, uint64_t act,
-                                                uint32_t intile, int *P, const int *NBL, const uint32_t *ENDS,
+                                                const int (&lc)[kNCellCodes], int *P, uint32_t *U,
                                                 const uint8_t *K4, unsigned *cursor)
 {
     constexpr int NC = TX * TY * TZ;
+    constexpr int kCap = kUnionsPerCell * NC;
+    // local key of vertex mu of down tetrahedron f (-1 when outside the tile)
+    auto vkey = [&](int f, int mu) {
+        const SiteRef R = down_vertex(f, mu);
+        const int l = R.cell == kSelf ? tid : lc[R.cell];
+        return l >= 0 ? 16 * l + R.site : -1;
+    };
     // Up tetrahedra: components from the table, roots at the smallest vertex.
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -322,37 +352,77 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     }
     if (tid == 0) *cursor = 0;
     __syncthreads();
-    // Down bonds with both ends in the tile (one active bond per iteration).
+    // Down tetrahedra, inside the tile: spanning edges, packed two 16-bit keys.
+    uint32_t un[12];
+    unsigned nun = 0;
     if (valid) {
-        uint32_t todo = (uint32_t)(act >> 24) & intile;
-        while (todo) {
-            const int jj = __ffs(todo) - 1;
-            todo &= todo - 1;
-            const uint32_t e = ENDS[jj];
-            const int ca = e & 0xFF, sa = (e >> 8) & 0xFF, cb = (e >> 16) & 0xFF, sb = e >> 24;
-            const int la = NBL[ca * NC + tid], lb = NBL[cb * NC + tid];
-            lds_unite<NC>(P, 16 * la + sa, 16 * lb + sb);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int k0 = vkey(f, 0), k1 = vkey(f, 1), k2 = vkey(f, 2), k3 = vkey(f, 3);
+            uint32_t inside = 0;  // bonds with both ends in the tile
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int a = pair_a(e), b = pair_b(e);
+                const int ka = a == 0 ? k0 : (a == 1 ? k1 : k2), kb = b == 1 ? k1 : (b == 2 ? k2 : k3);
+                inside |= (uint32_t)(ka >= 0 && kb >= 0) << e;
+            }
+            const uint32_t code = K4[(uint32_t)(act >> (24 + 6 * f)) & inside];
+#pragma unroll
+            for (int mu = 1; mu < 4; ++mu) {
+                const int rp = (code >> (2 * mu)) & 3;
+                const int kr = rp == 0 ? k0 : (rp == 1 ? k1 : k2);
+                const int km = mu == 1 ? k1 : (mu == 2 ? k2 : k3);
+                const bool use = rp != mu;
+                un[3 * f + mu - 1] = use ? ((uint32_t)kr << 16 | (uint32_t)km) : 0xFFFFFFFFu;
+                nun += use;
+            }
         }
     }
+    if (nun) {
+        unsigned at = atomicAdd(cursor, nun);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            if (un[k] == 0xFFFFFFFFu) continue;
+            if (at < (unsigned)kCap) U[at] = un[k];
+            else lds_unite<NC>(P, (int)(un[k] >> 16), (int)(un[k] & 0xFFFFu));
+            ++at;
+        }
+    }
+    __syncthreads();
+    const int nlist = min((int)*cursor, kCap);
+    for (int k = tid; k < nlist; k += NC) lds_unite<NC>(P, (int)(U[k] >> 16), (int)(U[k] & 0xFFFFu));
+    __syncthreads();
+    // Tile-local roots: written to the labels and back into the forest, so
+    // that every node then points straight at its root.
+    int r[16];
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) r[k] = lds_find<NC>(P, 16 * tid + k);
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) P[lds_pos<NC>(16 * tid + k)] = r[k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) r[k] = ti.global_site(r[k]);
+        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+    }
+    if (tid == 0) *cursor = 0;
     __syncthreads();
     int2 pr[12];
     unsigned npair = 0;
     if (valid) {
-        int r[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) r[k] = ti.global_site(lds_find<NC>(P, 16 * tid + k));
-        int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
         const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
         if (is_face_cell(lx, ly, lz, d)) {
             const int L = d.L;
             const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
             auto vertex_id = [&](int f, int mu, bool &outside) {
                 const SiteRef R = down_vertex(f, mu);
-                if (R.cell == kSelf) return r[R.site];
-                const int lc = NBL[R.cell * NC + tid];
-                if (lc >= 0) return ti.global_site(lds_find<NC>(P, 16 * lc + R.site));
+                if (R.cell == kSelf) return r[R.site] | kTag;
+                const int l = lc[R.cell];
+                if (l >= 0) return ti.global_site(P[lds_pos<NC>(16 * l + R.site)]) | kTag;
                 outside = true;
                 return nbr_site(R.cell, R.site, x, y, z, xm, ym, zm, L);
             };
@@ -380,7 +450,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         unsigned at = atomicAdd(cursor, npair);
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            if (pr[k].x >= 0) list[at++] = pr[k];
+            if (pr[k].x != -1) list[at++] = pr[k];
     }
     __syncthreads();
     if (tid == 0) d.pairs[(int64_t)tile * d.list_stride] = (int)*cursor;
@@ -395,14 +465,16 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 //               the workgroup first reduces per merged root in LDS, so a
 //               root shared by every pair (one giant cluster) receives one
 //               atomic per tile instead of one per pair;
-//   kPassStore  store that encoding in every local root of the list.
+//   kPassStore  store that encoding in every local root of the list (walks
+//               stop at the first stored encoding, so they shorten as the
+//               pass proceeds).
 enum GlobalPass : int { kPassUnite = 0, kPassMin = 1, kPassStore = 2 };
 
 template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
 {
     constexpr int H = 1024;
-    __shared__ int HK[H];
+    __shared__ int HK[PASS == kPassUnite ? 1 : H];
     __shared__ int HV[PASS == kPassMin ? H : 1];
     const int rep = c.tile_rep[blockIdx.x];
     if (c.state[rep]->remaining <= 0) return;
@@ -416,15 +488,25 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     if (PASS == kPassUnite) {
         for (int k = tid; k < n; k += kBlock) {
             const int2 p = list[k];
-            forest_unite(lab, endpoint_root(lab, p.x), endpoint_root(lab, p.y));
+            forest_unite(lab, name_root(lab, p.x), name_root(lab, p.y));
         }
         return;
     }
     if (n == 0) return;
-    for (int k = tid; k < H; k += kBlock) HK[k] = -1;
+    for (int k = tid; k < H; k += kBlock) {
+        HK[k] = -1;
+        if (PASS == kPassMin) HV[k] = INT32_MAX;
+    }
     __syncthreads();
     // key: merged root (min pass) or local root (store pass); value: the
     // smallest local root seen under that key (min pass)
+    auto act = [&](int key, int val) {
+        if (PASS == kPassMin) {
+            if (lab_load(lab, key) > kCanonBase + val) atomicMin(lab + key, kCanonBase + val);
+        } else {
+            lab_store(lab, key, encoded_canon(lab, key));
+        }
+    };
     auto add = [&](int key, int val) {
         uint32_t h = (uint32_t)key * 0x9E3779B1u;
         h ^= h >> 15;
@@ -437,19 +519,11 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
                 return;
             }
         }
-        // table full: act directly
-        if (PASS == kPassMin) {
-            if (lab_load(lab, key) > kCanonBase + val) atomicMin(lab + key, kCanonBase + val);
-        } else {
-            lab_store(lab, key, encoded_canon(lab, key));
-        }
+        act(key, val);  // table full: act directly
     };
-    if (PASS == kPassMin)
-        for (int k = tid; k < H; k += kBlock) HV[k] = INT32_MAX;
-    __syncthreads();
     for (int k = tid; k < 2 * n; k += kBlock) {
         const int2 p = list[k >> 1];
-        const int r = endpoint_root(lab, (k & 1) ? p.y : p.x);
+        const int r = name_root(lab, (k & 1) ? p.y : p.x);
         if (PASS == kPassMin) add(merged_root(lab, r), r);
         else add(r, r);
     }
@@ -457,12 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     for (int k = tid; k < H; k += kBlock) {
         const int key = HK[k];
         if (key < 0) continue;
-        if (PASS == kPassMin) {
-            const int v = HV[k];
-            if (lab_load(lab, key) > kCanonBase + v) atomicMin(lab + key, kCanonBase + v);
-        } else {
-            lab_store(lab, key, encoded_canon(lab, key));
-        }
+        act(key, PASS == kPassMin ? HV[k] : key);
     }
 }
 
