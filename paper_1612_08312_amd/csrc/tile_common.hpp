@@ -78,9 +78,21 @@ struct NbrCell {
     int lcell;  // local cell index in the tile, or -1 if outside
 };
 
+// Quotient a / b for 0 <= a < 2^24 and b >= 1 with a small quotient: a
+// float reciprocal gives it to within one, an integer check corrects it.
+__device__ __forceinline__ int small_div(int a, int b, float inv_b)
+{
+    int q = (int)((float)a * inv_b);
+    if (q * b > a) --q;
+    else if ((q + 1) * b <= a) ++q;
+    return q;
+}
+
 template <int TX, int TY, int TZ>
 struct TileIdx {
     int L, bx, by, bz;
+    int base;            // global index of the tile's first cell
+    float inv_L, inv_LL; // 1/L and 1/L^2
 
     __device__ __forceinline__ static TileIdx of(int tile, const RepDesc &d)
     {
@@ -90,6 +102,9 @@ struct TileIdx {
         tile /= d.ntx;
         t.by = tile % d.nty;
         t.bz = tile / d.nty;
+        t.base = ((t.bz * TZ) * t.L + t.by * TY) * t.L + t.bx * TX;
+        t.inv_L = 1.0f / (float)t.L;
+        t.inv_LL = 1.0f / (float)(t.L * t.L);
         return t;
     }
     __device__ __forceinline__ NbrCell at(int x, int y, int z) const
@@ -105,15 +120,20 @@ struct TileIdx {
     __device__ __forceinline__ int global_site(int l) const
     {
         const int lc = l >> 4;
-        const int x = bx * TX + lc % TX, y = by * TY + (lc / TX) % TY, z = bz * TZ + lc / (TX * TY);
-        return 16 * ((z * L + y) * L + x) + (l & 15);
+        const int lx = lc % TX, ly = (lc / TX) % TY, lz = lc / (TX * TY);
+        return 16 * (base + (lz * L + ly) * L + lx) + (l & 15);
     }
-    // Local key 16 c + k of a global site index known to lie in this tile.
+    // Local key 16 c + k of a global site index known to lie in this tile
+    // (offsets from the tile's first cell are below TZ L^2 < 2^24).
     __device__ __forceinline__ int local_key(int site) const
     {
-        const int cell = site >> 4;
-        const int x = cell % L, y = (cell / L) % L, z = cell / (L * L);
-        return 16 * (((z - bz * TZ) * TY + (y - by * TY)) * TX + (x - bx * TX)) + (site & 15);
+        const int off = (site >> 4) - base;
+        const int LL = L * L;
+        const int lz = small_div(off, LL, inv_LL);
+        const int rem = off - lz * LL;
+        const int ly = small_div(rem, L, inv_L);
+        const int lx = rem - ly * L;
+        return 16 * ((lz * TY + ly) * TX + lx) + (site & 15);
     }
     // The seven cells the bonds of cell (x, y, z) touch (periodic wrap).
     __device__ __forceinline__ void neighbours(int x, int y, int z, int cell, int lcell,
