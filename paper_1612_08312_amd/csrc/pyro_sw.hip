@@ -43,6 +43,7 @@ namespace {
 int fail(int status, const std::string &msg) { return record_error(status, msg.c_str()); }
 
 constexpr int kRing = 16384;  // device records per lattice before a forced drain
+constexpr int kMaxSlices = 8;  // concurrent slices of a group
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -232,12 +233,23 @@ struct pyro_sw {
     Timer timer;
 };
 
+// A slice of a group's members with its own chains, captured sweep and
+// internal stream: the slices of a group run concurrently, so the
+// latency-bound passes of one slice overlap the arithmetic of another.
+struct SubGroup {
+    ChainTables chains[3];  // Ising, XY, Heisenberg members of this slice
+    hipGraphExec_t exec = nullptr;
+    hipStream_t stream = nullptr;  // internal, default priority
+    hipEvent_t join = nullptr;
+};
+
 struct pyro_sw_group {
     std::vector<pyro_sw *> members;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    ChainTables chains[3];  // Ising, XY, Heisenberg
-    hipGraphExec_t exec = nullptr;
+    ChainTables chains[3];  // all members per model: tile shape and tuning key
+    std::vector<SubGroup> subs;
+    hipEvent_t fork = nullptr;
     std::vector<uint64_t> seen_versions;
     bool tables_dirty = true;
     RepState **d_members = nullptr;  // state pointer of every member (stream-ordered allocation)
@@ -836,6 +848,33 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
         auto it = g_tune_cache.find(tune_key(ct));
         ct.shape = it != g_tune_cache.end() ? it->second : kTile888;
     }
+    // slices: members dealt largest first to the lightest slice
+    const int nsub = std::min(n, kMaxSlices);
+    g->subs.resize(nsub);
+    std::vector<double> load(nsub, 0.0);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return g->members[a]->N > g->members[b]->N; });
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += (double)g->members[i]->N;
+        pyro_sw *h = g->members[i];
+        g->subs[k].chains[h->model - 1].reps.push_back(h);
+    }
+    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+    for (auto &sg : g->subs) {
+        for (int m = 0; m < 3; ++m) sg.chains[m].model = m + 1;
+        if (nsub > 1) {
+            ok = ok && hipStreamCreateWithFlags(&sg.stream, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&sg.join, hipEventDisableTiming) == hipSuccess;
+        }
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        pyro_sw_group_destroy(g);
+        return fail(PYRO_EDEVICE, "group stream or event creation failed");
+    }
     *out = g;
     return PYRO_OK;
 }
@@ -847,12 +886,15 @@ static int group_prepare(pyro_sw_group *g)
         for (size_t i = 0; i < g->members.size(); ++i)
             if (g->seen_versions[i] != g->members[i]->param_version) changed = true;
     if (!changed) return PYRO_OK;
-    if (g->exec) {
-        hipGraphExecDestroy(g->exec);
-        g->exec = nullptr;
-    }
     HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
-    for (auto &ct : g->chains) HIP_OR_FAIL(&g->broken, build_group_chain(ct, ct.shape, g->stream));
+    for (auto &sg : g->subs) {
+        if (sg.exec) {
+            hipGraphExecDestroy(sg.exec);
+            sg.exec = nullptr;
+        }
+        for (int m = 0; m < 3; ++m)
+            HIP_OR_FAIL(&g->broken, build_group_chain(sg.chains[m], g->chains[m].shape, g->stream));
+    }
     g->seen_versions.clear();
     for (auto *h : g->members) g->seen_versions.push_back(h->param_version);
     g->tables_dirty = false;
@@ -863,22 +905,35 @@ static int group_prepare(pyro_sw_group *g)
 static int group_run(pyro_sw_group *g, int64_t reps)
 {
     Timer &tm = g->timer;
-    if (tm.mask) {
+    if (tm.mask) {  // every kernel in order on the group's stream
         const LaunchHook hook = hook_of(tm, g->stream);
         for (int64_t k = 0; k < reps; ++k) {
-            for (auto &ct : g->chains) HIP_OR_FAIL(&g->broken, launch_chain_sweep(ct.chain, g->stream, hook));
+            for (auto &sg : g->subs)
+                for (auto &ct : sg.chains) HIP_OR_FAIL(&g->broken, launch_chain_sweep(ct.chain, g->stream, hook));
             if (tm.inflight.size() > 8192) HIP_OR_FAIL(&g->broken, tm.collect());
         }
         return PYRO_OK;
     }
-    if (!g->exec) {
+    for (auto &sg : g->subs) {
+        if (sg.exec) continue;
         Chain cs[3];
         int nc = 0;
-        for (auto &ct : g->chains)
+        for (auto &ct : sg.chains)
             if (ct.chain.nreps > 0) cs[nc++] = ct.chain;
-        HIP_OR_FAIL(&g->broken, capture_sweep(cs, nc, &g->exec));
+        HIP_OR_FAIL(&g->broken, capture_sweep(cs, nc, &sg.exec));
     }
-    for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(g->exec, g->stream));
+    if (g->subs.size() == 1) {
+        for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(g->subs[0].exec, g->stream));
+        return PYRO_OK;
+    }
+    // fork the slices off the group's stream and join them back
+    HIP_OR_FAIL(&g->broken, hipEventRecord(g->fork, g->stream));
+    for (auto &sg : g->subs) {
+        HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(sg.stream, g->fork, 0));
+        for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(sg.exec, sg.stream));
+        HIP_OR_FAIL(&g->broken, hipEventRecord(sg.join, sg.stream));
+        HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(g->stream, sg.join, 0));
+    }
     return PYRO_OK;
 }
 
@@ -1053,8 +1108,14 @@ int pyro_sw_group_destroy(pyro_sw_group *g)
     int rc = PYRO_OK;
     if (g->stream && hipStreamSynchronize(g->stream) != hipSuccess) rc = fail(PYRO_EDEVICE, "synchronize failed");
     g->timer.release();
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    for (auto &ct : g->chains) free_tables(ct);
+    for (auto &sg : g->subs) {
+        if (sg.stream) hipStreamSynchronize(sg.stream);
+        if (sg.exec) hipGraphExecDestroy(sg.exec);
+        for (auto &ct : sg.chains) free_tables(ct);
+        if (sg.join) hipEventDestroy(sg.join);
+        if (sg.stream) hipStreamDestroy(sg.stream);
+    }
+    if (g->fork) hipEventDestroy(g->fork);
     if (g->d_members) hipFreeAsync(g->d_members, g->stream);
     if (g->own_stream) hipStreamDestroy(g->stream);
     delete g;
