@@ -490,6 +490,91 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 //               pass proceeds).
 enum GlobalPass : int { kPassUnite = 0, kPassMin = 1, kPassStore = 2 };
 
+// Unite pass of one tile (kBlock threads).  The pairs of a tile mostly share
+// a few local roots, so hooking them one by one makes the tile's threads
+// race for the same roots.  Instead, the distinct local roots of the list
+// are grouped by the list's pairs in an LDS union-find, each group picks the
+// member of smallest link priority (to 22 bits) as representative, and
+// every other member is united with it: the hooks of one tile then target
+// distinct roots.  Pairs beyond the LDS tables are united directly.
+__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, const int2 *list, int n, int tid)
+{
+    constexpr int H = 1024;           // root slots
+    constexpr int kMaxListed = 1024;  // pairs kept in LDS
+    __shared__ int HK[H];             // local root of the slot, -1 if free
+    __shared__ int HP[H];             // LDS parent slot
+    __shared__ uint32_t BEST[H];      // per group: (priority high bits | slot) minimum
+    __shared__ int16_t PA[kMaxListed], PB[kMaxListed];
+    for (int k = tid; k < H; k += kBlock) {
+        HK[k] = -1;
+        HP[k] = k;
+        BEST[k] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    auto insert = [&](int key) {
+        uint32_t h = (uint32_t)key * 0x9E3779B1u;
+        h ^= h >> 15;
+        for (int probe = 0; probe < 32; ++probe) {
+            const int slot = (int)((h + (uint32_t)probe) & (H - 1));
+            int prev = HK[slot];
+            if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
+            if (prev == -1 || prev == key) return slot;
+        }
+        return -1;
+    };
+    for (int k = tid; k < n; k += kBlock) {
+        const int2 p = list[k];
+        const int ra = name_root(lab, p.x), rb = name_root(lab, p.y);
+        const int sa = ra == rb ? -1 : insert(ra), sb = ra == rb ? -1 : insert(rb);
+        const bool listed = k < kMaxListed && sa >= 0 && sb >= 0;
+        if (!listed && ra != rb) forest_unite(lab, ra, rb);
+        if (k < kMaxListed) {
+            PA[k] = (int16_t)(listed ? sa : -1);
+            PB[k] = (int16_t)(listed ? sb : -1);
+        }
+    }
+    __syncthreads();
+    auto slot_find = [&](int x) {
+        for (int it = 0; it < H; ++it) {
+            const int p = HP[x];
+            if (p == x) return x;
+            const int gp = HP[p];
+            if (gp != p) HP[x] = gp;
+            x = p;
+        }
+        return x;
+    };
+    const int nl = min(n, kMaxListed);
+    for (int k = tid; k < nl; k += kBlock) {
+        int a = PA[k], b = PB[k];
+        if (a < 0) continue;
+        for (int it = 0; it < H; ++it) {
+            a = slot_find(a);
+            b = slot_find(b);
+            if (a == b) break;
+            if (a < b) {
+                const int t = a;
+                a = b;
+                b = t;
+            }
+            const int old = atomicMin(&HP[a], b);
+            if (old == a) break;
+            a = old;
+        }
+    }
+    __syncthreads();
+    for (int s = tid; s < H; s += kBlock) {
+        if (HK[s] < 0) continue;
+        atomicMin(&BEST[slot_find(s)], (link_priority(HK[s]) & ~(uint32_t)(H - 1)) | (uint32_t)s);
+    }
+    __syncthreads();
+    for (int s = tid; s < H; s += kBlock) {
+        if (HK[s] < 0) continue;
+        const int rep = (int)(BEST[slot_find(s)] & (uint32_t)(H - 1));
+        if (rep != s) forest_unite(lab, HK[s], HK[rep]);
+    }
+}
+
 template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
 {
@@ -506,10 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     const int tid = threadIdx.x;
     int32_t *lab = d.label;
     if (PASS == kPassUnite) {
-        for (int k = tid; k < n; k += kBlock) {
-            const int2 p = list[k];
-            forest_unite(lab, name_root(lab, p.x), name_root(lab, p.y));
-        }
+        unite_tile_pairs(lab, list, n, tid);
         return;
     }
     if (n == 0) return;
