@@ -49,6 +49,53 @@ def bytes_per_site(shape):
     }
 
 
+# HBM traffic of the dominant kernel per launch (one L=128 lattice), from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of `bench.py --pmc-probe`,
+# each scaled by the same counter's reading for the probe's 256 MiB copy.
+# Valid only for the kernel sources they were taken with (fingerprint).
+MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
+    "local": ("0668037b6509e3bb", 216956507),  # profiles/k_local_ising_L128_traffic.md
+}
+
+
+def kernel_fingerprint():
+    """SHA-256 over the HIP sources of the library (names and contents)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1612_08312_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_probe():
+    """Workload for counter collection: a 256 MiB device copy (calibration),
+    then 4 sweeps of the bench's first L=128 lattice with every kernel
+    launched directly (no graph) after 30 graph sweeps."""
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    torch.cuda.set_device(0)
+    a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    cfg = workloads.ISING_L128
+    lt = pyrosw.Lattice(L=128, model=1, T=cfg["temps"][2], seed=cfg["seeds"][2], start=cfg["start"])
+    lt.sweep(30)
+    lt.moments()
+    pyrosw.pyro_sw_set_timing(lt.h, -1)
+    lt.sweep(4)
+    pyrosw.pyro_sw_kernel_times(lt.h)
+    lt.close()
+    log("pmc probe done, kernel fingerprint", kernel_fingerprint())
+
+
 SWEEP_BYTES_PER_SITE = 11.0  # whole-sweep model: read s, write/read labels, read/write s
 
 
@@ -203,6 +250,34 @@ def serving_vs_plain(n_jobs, budget_gb, quantum_ms, dev):
     }
 
 
+def on_throughput(sweeps, stream, dev):
+    """XY (T = 2.0285) and Heisenberg (T = 1.31695) on the L = 64 pyrochlore
+    lattice (4,194,304 sites each, random start, FP32 spins, FP64 moments):
+    spin-updates/s of each, one lattice at a time, after 20 warm-up sweeps."""
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    out = {}
+    for cfg in workloads.ON_L64:
+        name = "xy" if cfg["model"] == 2 else "heisenberg"
+        lt = pyrosw.Lattice(L=cfg["L"], model=cfg["model"], T=cfg["T"], J=cfg["J"], seed=cfg["seed"],
+                            start=cfg["start"], device=dev, stream=stream)
+        lt.sweep(20)
+        lt.moments()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lt.sweep(sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = lt.moments()
+        lt.close()
+        out[name] = {"T": cfg["T"], "spin_updates_per_s": lt.N * sweeps / dt, "us_per_sweep": dt / sweeps * 1e6,
+                     "mean_m2": float(rec["m2"].mean())}
+    out.update(workload="on_pyrochlore_L64", L=64, sweeps=sweeps)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,10 +292,15 @@ def main():
                     help="jobs of the Poisson serving stream for the served-vs-plain comparison (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the job server")
     ap.add_argument("--serve-quantum-ms", type=float, default=20.0, help="lane quantum of the job server")
+    ap.add_argument("--on-sweeps", type=int, default=500, help="sweeps of the XY and Heisenberg L=64 leg (0: skip)")
+    ap.add_argument("--pmc-probe", action="store_true", help="run the counter-collection workload and exit")
     ap.add_argument("--roofline-steps", type=int, default=200,
                     help="steps of the pass that times the dominant kernel with HIP events")
     args = ap.parse_args()
 
+    if args.pmc_probe:
+        pmc_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent lattices would shard by replica; see the design notes)", file=sys.stderr)
@@ -290,6 +370,10 @@ def main():
     launches_per_step = max(dom_n, 1) / roof_steps
     bytes_per_launch = byte_model.get(dominant, 0.0) * N * len(lats) / launches_per_step
     achieved = bytes_per_launch / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
+    traffic = None
+    fp, tbytes = MEASURED_TRAFFIC.get(dominant, (None, None))
+    if fp == kernel_fingerprint() and launches_per_step == len(lats):
+        traffic = tbytes
     binder = {}
     for T, r in zip(temps, recs):
         half = r[len(r) // 2:]
@@ -327,7 +411,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "alg_bytes_per_site": byte_model.get(dominant, 0.0),
             "mean_launch_us": dom_avg_s * 1e6,
             "timed_launches": dom_n,
@@ -337,6 +421,9 @@ def main():
         "binder_U_second_half": binder,
         "kernel_mean_us_probe": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},
     }
+    if args.on_sweeps > 0:
+        log(f"bench: XY and Heisenberg L=64, {args.on_sweeps} sweeps each")
+        out["on"] = on_throughput(args.on_sweeps, stream, dev)
     if args.batch_sweeps > 0:
         log(f"bench: 96-replica batch, {args.batch_sweeps} sweeps, batched then plain")
         out["batched"] = batched_vs_plain(args.batch_sweeps, stream, dev)

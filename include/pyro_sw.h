@@ -196,6 +196,14 @@ int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, doub
  *                          no result.  shapes_out[3] (may be NULL) receives
  *                          the shapes for Ising, XY, Heisenberg.
  *   pyro_sw_group_set_tile_shape  fix the shape of one model's lattices.
+ *   pyro_sw_group_set_slices  run the members as nslices (1..8) slices,
+ *                          each with its own captured sweep and internal
+ *                          stream, forked from and joined to the group's
+ *                          stream on every call, so that the latency-bound
+ *                          passes of one slice overlap the arithmetic of
+ *                          another (members are dealt largest first to the
+ *                          lightest slice; default min(n, 8)).  Changes speed
+ *                          only, never results.
  *   pyro_sw_group_set_timing / pyro_sw_group_kernel_times  as for a handle.
  *   pyro_sw_group_destroy  frees the group only (NULL is a no-op).
  * Errors: PYRO_EINVAL (arguments), PYRO_ESTATE (a member failed or is busy),
@@ -206,6 +214,7 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
 int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_member);
 int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out);
 int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape);
+int pyro_sw_group_set_slices(pyro_sw_group *g, int nslices);
 int pyro_sw_group_set_timing(pyro_sw_group *g, int kernel_mask);
 int pyro_sw_group_kernel_times(pyro_sw_group *g, const char **names, int64_t *launches, double *ms,
                                int cap, int *n_out);

@@ -599,6 +599,52 @@ std::string tune_key(const ChainTables &ct)
 
 }  // namespace
 
+// (Re)deal a group's members to nslices slices, largest first to the
+// lightest slice; every slice beyond the first gets its own stream.
+static void drop_slices(pyro_sw_group *g)
+{
+    for (auto &sg : g->subs) {
+        if (sg.stream) hipStreamSynchronize(sg.stream);
+        if (sg.exec) hipGraphExecDestroy(sg.exec);
+        for (auto &ct : sg.chains) free_tables(ct);
+        if (sg.join) hipEventDestroy(sg.join);
+        if (sg.stream) hipStreamDestroy(sg.stream);
+    }
+    g->subs.clear();
+}
+
+static int make_slices(pyro_sw_group *g, int nslices)
+{
+    const int n = (int)g->members.size();
+    drop_slices(g);
+    g->subs.resize(nslices);
+    std::vector<double> load(nslices, 0.0);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return g->members[a]->N > g->members[b]->N; });
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += (double)g->members[i]->N;
+        pyro_sw *h = g->members[i];
+        g->subs[k].chains[h->model - 1].reps.push_back(h);
+    }
+    bool ok = g->fork || hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+    for (auto &sg : g->subs) {
+        for (int m = 0; m < 3; ++m) sg.chains[m].model = m + 1;
+        if (nslices > 1) {
+            ok = ok && hipStreamCreateWithFlags(&sg.stream, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&sg.join, hipEventDisableTiming) == hipSuccess;
+        }
+    }
+    g->tables_dirty = true;
+    if (!ok) {
+        (void)hipGetLastError();
+        return fail(PYRO_EDEVICE, "group stream or event creation failed");
+    }
+    return PYRO_OK;
+}
+
 extern "C" {
 
 int pyro_sw_workspace_size(int L, int model, size_t *spin_bytes, size_t *work_bytes)
@@ -848,32 +894,9 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
         auto it = g_tune_cache.find(tune_key(ct));
         ct.shape = it != g_tune_cache.end() ? it->second : kTile888;
     }
-    // slices: members dealt largest first to the lightest slice
-    const int nsub = std::min(n, kMaxSlices);
-    g->subs.resize(nsub);
-    std::vector<double> load(nsub, 0.0);
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return g->members[a]->N > g->members[b]->N; });
-    for (int i : order) {
-        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += (double)g->members[i]->N;
-        pyro_sw *h = g->members[i];
-        g->subs[k].chains[h->model - 1].reps.push_back(h);
-    }
-    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
-    for (auto &sg : g->subs) {
-        for (int m = 0; m < 3; ++m) sg.chains[m].model = m + 1;
-        if (nsub > 1) {
-            ok = ok && hipStreamCreateWithFlags(&sg.stream, hipStreamNonBlocking) == hipSuccess;
-            ok = ok && hipEventCreateWithFlags(&sg.join, hipEventDisableTiming) == hipSuccess;
-        }
-    }
-    if (!ok) {
-        (void)hipGetLastError();
+    if (int rc = make_slices(g, std::min(n, kMaxSlices))) {
         pyro_sw_group_destroy(g);
-        return fail(PYRO_EDEVICE, "group stream or event creation failed");
+        return rc;
     }
     *out = g;
     return PYRO_OK;
@@ -997,6 +1020,15 @@ int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_m
     return PYRO_OK;
 }
 
+int pyro_sw_group_set_slices(pyro_sw_group *g, int nslices)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (g->broken) return fail(PYRO_ESTATE, "group failed earlier");
+    if (nslices < 1 || nslices > kMaxSlices) return fail(PYRO_EINVAL, "nslices must be in [1, 8]");
+    HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+    return make_slices(g, std::min(nslices, (int)g->members.size()));
+}
+
 int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape)
 {
     if (!g) return fail(PYRO_EINVAL, "group is NULL");
@@ -1108,13 +1140,7 @@ int pyro_sw_group_destroy(pyro_sw_group *g)
     int rc = PYRO_OK;
     if (g->stream && hipStreamSynchronize(g->stream) != hipSuccess) rc = fail(PYRO_EDEVICE, "synchronize failed");
     g->timer.release();
-    for (auto &sg : g->subs) {
-        if (sg.stream) hipStreamSynchronize(sg.stream);
-        if (sg.exec) hipGraphExecDestroy(sg.exec);
-        for (auto &ct : sg.chains) free_tables(ct);
-        if (sg.join) hipEventDestroy(sg.join);
-        if (sg.stream) hipStreamDestroy(sg.stream);
-    }
+    drop_slices(g);
     if (g->fork) hipEventDestroy(g->fork);
     if (g->d_members) hipFreeAsync(g->d_members, g->stream);
     if (g->own_stream) hipStreamDestroy(g->stream);

@@ -229,7 +229,8 @@ int launch_quanta(pyro_sw_server *s, bool *progress)
             ln.g = nullptr;
             std::vector<pyro_sw *> hs;
             for (Job *j : ln.members) hs.push_back(j->h);
-            const int rc = pyro_sw_group_create(&ln.g, hs.data(), (int)hs.size(), ln.st);
+            int rc = pyro_sw_group_create(&ln.g, hs.data(), (int)hs.size(), ln.st);
+            if (!rc) rc = pyro_sw_group_set_slices(ln.g, 1);  // the lanes already run concurrently
             if (rc) return server_fail(s, rc == PYRO_EDEVICE ? rc : PYRO_EDEVICE, "lane group creation failed");
             ln.dirty = false;
         }

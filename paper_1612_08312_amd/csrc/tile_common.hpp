@@ -30,7 +30,7 @@ namespace pyro {
 template <int NC>
 __device__ __forceinline__ int lds_pos(int key)
 {
-    return (key & 15) * NC + (key >> 4);
+    return (int)(((unsigned)key & 15u) * NC + ((unsigned)key >> 4));
 }
 
 // Every walk below is capped far above any reachable depth (a forest over n
@@ -119,8 +119,8 @@ struct TileIdx {
     // Global site index of local key l = 16 c + k.
     __device__ __forceinline__ int global_site(int l) const
     {
-        const int lc = l >> 4;
-        const int lx = lc % TX, ly = (lc / TX) % TY, lz = lc / (TX * TY);
+        const unsigned lc = (unsigned)l >> 4;  // keys are non-negative; unsigned keeps % and / to masks and shifts
+        const int lx = (int)(lc % TX), ly = (int)((lc / TX) % TY), lz = (int)(lc / (TX * TY));
         return 16 * (base + (lz * L + ly) * L + lx) + (l & 15);
     }
     // Local key 16 c + k of a global site index known to lie in this tile

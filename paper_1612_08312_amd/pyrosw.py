@@ -44,7 +44,7 @@ EXPORTS = (
     "pyro_sw_destroy", "pyro_sw_strerror", "pyro_sw_last_error", "pyro_sw_set_tile_shape",
     "pyro_sw_group_create", "pyro_sw_group_sweep", "pyro_sw_group_autotune",
     "pyro_sw_group_set_tile_shape", "pyro_sw_group_set_timing", "pyro_sw_group_kernel_times",
-    "pyro_sw_group_destroy",
+    "pyro_sw_group_destroy", "pyro_sw_group_set_slices",
     "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
     "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
 )
@@ -110,6 +110,7 @@ def load_library():
     lib.pyro_sw_group_sweep.argtypes = [vp, i64, P(i64)]
     lib.pyro_sw_group_autotune.argtypes = [vp, i32, P(i32)]
     lib.pyro_sw_group_set_tile_shape.argtypes = [vp, i32, i32]
+    lib.pyro_sw_group_set_slices.argtypes = [vp, i32]
     lib.pyro_sw_group_set_timing.argtypes = [vp, i32]
     lib.pyro_sw_group_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_group_destroy.argtypes = [vp]
@@ -283,6 +284,10 @@ def pyro_sw_group_kernel_times(g) -> dict:
     return _kernel_times(load_library().pyro_sw_group_kernel_times, g, "pyro_sw_group_kernel_times")
 
 
+def pyro_sw_group_set_slices(g, nslices: int):
+    _check(load_library().pyro_sw_group_set_slices(g, int(nslices)), "pyro_sw_group_set_slices")
+
+
 def pyro_sw_group_destroy(g):
     if g is not None and g.value:
         _check(load_library().pyro_sw_group_destroy(g), "pyro_sw_group_destroy")
@@ -381,6 +386,9 @@ class Group:
 
     def set_tile_shape(self, model, shape):
         pyro_sw_group_set_tile_shape(self.g, model, shape)
+
+    def set_slices(self, nslices):
+        pyro_sw_group_set_slices(self.g, nslices)
 
     def close(self):
         if getattr(self, "g", None) is not None:

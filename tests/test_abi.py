@@ -88,3 +88,8 @@ def test_server_null_calls():
     assert lib.pyro_sw_server_step(None, 0.0, None, None) == pyrosw.PYRO_EINVAL
     assert lib.pyro_sw_server_destroy(None) == pyrosw.PYRO_OK
     assert ctypes.sizeof(pyrosw.JobSpec) == 48 and ctypes.sizeof(pyrosw.JobStatus) == 64
+
+
+def test_group_set_slices_null():
+    lib = pyrosw.load_library()
+    assert lib.pyro_sw_group_set_slices(None, 2) == pyrosw.PYRO_EINVAL

@@ -119,3 +119,26 @@ def test_long_run_ring_drains():
     o = oracle.Oracle(L=1, model=1, T=4.2139, seed=41, start=1)
     a.sweep(20000)
     same_records(a.moments(), o.sweep(20000))
+
+
+@pytest.mark.parametrize("nslices", [1, 3, 8])
+def test_slices_change_no_result(nslices):
+    """The members of a group run as concurrent slices (own stream and
+    captured sweep each); any slice count gives the same records."""
+    ref = [lat(**kw) for kw in MIX]
+    g0 = pyrosw.Group(ref)
+    g0.set_slices(1)
+    g0.sweep(17)
+    want = [lt.moments() for lt in ref]
+    g0.close()
+    lats = [lat(**kw) for kw in MIX]
+    g = pyrosw.Group(lats)
+    g.set_slices(nslices)
+    g.sweep(9)
+    g.set_slices(max(1, nslices - 1))  # re-dealing between calls keeps every trajectory
+    g.sweep(8)
+    for lt, w in zip(lats, want):
+        same_records(lt.moments(), w)
+    g.close()
+    for lt in ref + lats:
+        lt.close()
