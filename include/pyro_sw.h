@@ -154,7 +154,7 @@ int pyro_sw_set_temperature(pyro_sw *h, double T);
  * The shape changes speed only, never results (labels are canonical and all
  * draws are keyed by sweep and site or bond).  A new handle uses 8x8x8.
  */
-enum { PYRO_TILE_8x8x4 = 0, PYRO_TILE_8x4x4 = 1, PYRO_TILE_4x4x4 = 2, PYRO_TILE_8x8x8 = 3 };
+enum { PYRO_TILE_8x8x4 = 0, PYRO_TILE_8x4x4 = 1, PYRO_TILE_4x4x4 = 2, PYRO_TILE_8x8x8 = 3, PYRO_TILE_16x8x8 = 4 };
 int pyro_sw_set_tile_shape(pyro_sw *h, int shape);
 
 /* Number of sites N and global index of the next sweep. */

@@ -32,13 +32,13 @@ constexpr int kBlock = 256;  // threads of the per-cell and per-call kernels
 __host__ __device__ inline int blocks_for(int64_t n, int per_block = kBlock) { return (int)((n + per_block - 1) / per_block); }
 
 // Tile shapes (cells per tile edge) the library is built for.
-enum TileShape : int { kTile884 = 0, kTile844 = 1, kTile444 = 2, kTile888 = 3, kNumTileShapes };
+enum TileShape : int { kTile884 = 0, kTile844 = 1, kTile444 = 2, kTile888 = 3, kTile1688 = 4, kNumTileShapes };
 struct TileDims {
     int x, y, z;
 };
 inline TileDims tile_dims(int shape)
 {
-    static const TileDims d[kNumTileShapes] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {8, 8, 8}};
+    static const TileDims d[kNumTileShapes] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {8, 8, 8}, {16, 8, 8}};
     return d[shape];
 }
 

@@ -88,7 +88,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     const float x0 = d.x0;
     const int tid = threadIdx.x;
     const int L = d.L;
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int lcid = cell_of_thread<TX, TY, TZ>(tid);  // face cells in the first waves
+    const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
     const int cell = (z * L + y) * L + x;
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
         float r[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
-        ti.neighbours(x, y, z, cell, tid, nb);
+        ti.neighbours(x, y, z, cell, lcid, nb);
 #pragma unroll
         for (int q = 0; q < kNCellCodes; ++q) lc[q] = nb[q].lcell;
         float own[NV][16];
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
             }
         }
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, valid, cell, x, y, z, act, lc, P, U, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, x, y, z, act, lc, P, U, K4, &cursor);
     const double b = block_sum<double>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }

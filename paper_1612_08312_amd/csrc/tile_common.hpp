@@ -324,6 +324,36 @@ __device__ __forceinline__ int name_root(const int32_t *lab, int name)
     return (name & kTag) ? (name & kIdxMask) : endpoint_root(lab, name);
 }
 
+// Thread -> local cell order of the tile pass: the cells of the low faces
+// first (in cell order), then the others.  Only low-face cells own crossing
+// bonds, so the emission of crossing pairs runs in the first few waves and
+// the other waves skip it; the low faces are whole rows of cells, so the
+// spin loads of a wave stay row-contiguous.
+template <int TX, int TY, int TZ>
+struct FaceFirst {
+    uint16_t c[TX * TY * TZ];
+};
+template <int TX, int TY, int TZ>
+__host__ __device__ constexpr FaceFirst<TX, TY, TZ> make_face_first()
+{
+    FaceFirst<TX, TY, TZ> t{};
+    int n = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int c = 0; c < TX * TY * TZ; ++c) {
+            const bool face = c % TX == 0 || (c / TX) % TY == 0 || c / (TX * TY) == 0;
+            if (face == (pass == 0)) t.c[n++] = (uint16_t)c;
+        }
+    return t;
+}
+template <int TX, int TY, int TZ>
+__constant__ FaceFirst<TX, TY, TZ> kFaceFirst = make_face_first<TX, TY, TZ>();
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ int cell_of_thread(int tid)
+{
+    return kFaceFirst<TX, TY, TZ>.c[tid];
+}
+
 // ------------------------------------------------------ tile components ---
 // Union-list entries per cell of a tile; unions beyond the list are done by
 // the thread that found them.
@@ -350,7 +380,7 @@ constexpr int kUnionsPerCell = 8;
 // none repeated.
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
-                                                bool valid, int cell, int x, int y, int z, uint64_t act,
+                                                int lcid, bool valid, int cell, int x, int y, int z, uint64_t act,
                                                 const int (&lc)[kNCellCodes], int *P, uint32_t *U,
                                                 const uint8_t *K4, unsigned *cursor)
 {
@@ -359,16 +389,16 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     // local key of vertex mu of down tetrahedron f (-1 when outside the tile)
     auto vkey = [&](int f, int mu) {
         const SiteRef R = down_vertex(f, mu);
-        const int l = R.cell == kSelf ? tid : lc[R.cell];
+        const int l = R.cell == kSelf ? lcid : lc[R.cell];
         return l >= 0 ? 16 * l + R.site : -1;
     };
     // Up tetrahedra: components from the table, roots at the smallest vertex.
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
-        const int base = 16 * tid + 4 * f;
+        const int base = 16 * lcid + 4 * f;
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + tid] = base + ((code >> (2 * mu)) & 3);
+        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + lcid] = base + ((code >> (2 * mu)) & 3);
     }
     if (tid == 0) *cursor = 0;
     __syncthreads();
@@ -417,12 +447,12 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     int r[16];
     if (valid) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) r[k] = lds_find<NC>(P, 16 * tid + k);
+        for (int k = 0; k < 16; ++k) r[k] = lds_find<NC>(P, 16 * lcid + k);
     }
     __syncthreads();
     if (valid) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) P[lds_pos<NC>(16 * tid + k)] = r[k];
+        for (int k = 0; k < 16; ++k) P[lds_pos<NC>(16 * lcid + k)] = r[k];
 #pragma unroll
         for (int k = 0; k < 16; ++k) r[k] = ti.global_site(r[k]);
         int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
@@ -434,7 +464,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     int2 pr[12];
     unsigned npair = 0;
     if (valid) {
-        const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+        const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
         if (is_face_cell(lx, ly, lz, d)) {
             const int L = d.L;
             const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
@@ -645,6 +675,7 @@ hipError_t with_tile_shape(int shape, Args &&...args)
     case kTile844: return F::template run<8, 4, 4>(args...);
     case kTile444: return F::template run<4, 4, 4>(args...);
     case kTile888: return F::template run<8, 8, 8>(args...);
+    case kTile1688: return F::template run<16, 8, 8>(args...);
     default: return F::template run<8, 8, 4>(args...);
     }
 }

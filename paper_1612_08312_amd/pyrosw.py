@@ -66,8 +66,8 @@ class JobStatus(ctypes.Structure):
                 ("reserved", ctypes.c_int), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_done", ctypes.c_double)]
 
-PYRO_TILE_8x8x4, PYRO_TILE_8x4x4, PYRO_TILE_4x4x4, PYRO_TILE_8x8x8 = 0, 1, 2, 3
-TILE_SHAPES = {0: "8x8x4", 1: "8x4x4", 2: "4x4x4", 3: "8x8x8"}
+PYRO_TILE_8x8x4, PYRO_TILE_8x4x4, PYRO_TILE_4x4x4, PYRO_TILE_8x8x8, PYRO_TILE_16x8x8 = 0, 1, 2, 3, 4
+TILE_SHAPES = {0: "8x8x4", 1: "8x4x4", 2: "4x4x4", 3: "8x8x8", 4: "16x8x8"}
 
 
 class PyroSWError(RuntimeError):

@@ -79,7 +79,7 @@ def test_group_per_member_counts_and_oracle():
 @pytest.mark.parametrize("model,L", [(1, 6), (1, 9), (2, 5), (3, 4)])
 def test_tile_shapes_do_not_change_results(model, L):
     ref = None
-    for shape in range(4):
+    for shape in range(len(pyrosw.TILE_SHAPES)):
         x = lat(L=L, model=model, T=workloads.TC[model], seed=21, start=1)
         x.set_tile_shape(shape)
         x.sweep(25)
