@@ -8,9 +8,10 @@
 //                  each up tetrahedron with a K4 component table, unite the
 //                  down-tetrahedron bonds inside the tile in an LDS forest,
 //                  write every site's tile-local root as a global site index
-//                  and record the active bonds that leave the tile.  The
+//                  and list the tile's crossing pairs (tile_components).  The
 //                  parallel-bond count is the energy of the incoming state.
-//   merge / canonical passes over the tile-crossing bonds (tile_common.hpp).
+//   k_forest       unite, minimum and store passes over the crossing lists
+//                  (tile_common.hpp).
 //   k_coins        flip coins (tile_common.hip).
 //   k_flip_ising   one workgroup per tile: canonical label of every site from
 //                  an LDS copy of the tile's labels, coin, XOR flip of the

@@ -89,18 +89,18 @@ struct Chain {
     int ntile_blocks, ncell_blocks, ncoin_blocks;
 };
 
-// Kernel ids for timing.
+// Kernel ids for timing (names in init.hip).
 enum KernelId : int {
     kKInit = 0,
-    kKLocal,
-    kKUnite,
+    kKLocal,     // tile pass
+    kKUnite,     // forest unite pass
     kKCoins,
     kKFlip,
-    kKEnergy,
+    kKEnergy,    // energy tail
     kKFinalize,
-    kKAxis,
-    kKCompress,
-    kKCanonMin,
+    kKAxis,      // O(n) axis
+    kKCompress,  // forest store pass ("canon_store")
+    kKCanonMin,  // forest minimum pass
     kNumKernels
 };
 const char *kernel_name(int id);

@@ -1,6 +1,7 @@
-// Model-independent launchers of the tiled sweep: the merge of tile-crossing
-// bonds, the flip coins, the label compression used when the host reads
-// labels, and the dispatch of one sweep of a chain to its model.
+// Model-independent launchers of the tiled sweep: the passes over the
+// tiles' crossing lists, the flip coins, the canonical labels the host reads
+// (written to a separate buffer), and the dispatch of one sweep of a chain to
+// its model.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

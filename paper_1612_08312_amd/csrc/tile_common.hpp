@@ -150,22 +150,6 @@ struct TileIdx {
     }
 };
 
-// Endpoints of the 24 down-tetrahedron bonds of a cell (bond 24 + jj):
-// bytes (cell code of A, site of A, cell code of B, site of B).
-struct DownEnds {
-    uint32_t v[24];
-};
-__host__ __device__ constexpr DownEnds make_down_ends()
-{
-    DownEnds t{};
-    for (int jj = 0; jj < 24; ++jj) {
-        const SiteRef A = bond_end_a(24 + jj), B = bond_end_b(24 + jj);
-        t.v[jj] = (uint32_t)A.cell | (uint32_t)A.site << 8 | (uint32_t)B.cell << 16 | (uint32_t)B.site << 24;
-    }
-    return t;
-}
-static __constant__ DownEnds kDownEnds = make_down_ends();
-
 // Only cells on a low face of a tile own bonds that leave the tile.
 __device__ __forceinline__ bool is_face_cell(int lx, int ly, int lz, const RepDesc &d)
 {
