@@ -37,8 +37,7 @@ template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
-    constexpr int NS = 16 * NC;
-    __shared__ int P[NS];
+    __shared__ uint32_t P[kForestSlots<NC>];
     __shared__ uint32_t SM[NC];
     __shared__ uint32_t U[kUnionsPerCell * NC];
     __shared__ uint8_t K4[64];

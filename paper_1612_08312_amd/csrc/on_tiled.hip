@@ -70,8 +70,7 @@ template <int NV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
-    constexpr int NS = 16 * NC;
-    __shared__ int P[NS];
+    __shared__ uint32_t P[kForestSlots<NC>];
     __shared__ uint32_t U[kUnionsPerCell * NC];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];

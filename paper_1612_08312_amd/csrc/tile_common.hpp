@@ -24,13 +24,35 @@
 namespace pyro {
 
 // The tile forest is keyed by the canonical local index key = 16 c + k (cell
-// c of the tile, site k), whose order follows the global site order, but is
-// stored at position k * NC + c so that the lanes of a wave, which own
-// consecutive cells, touch consecutive LDS banks.
+// c of the tile, site k), whose order follows the global site order.  Node
+// key sits at slot key + c = 17 c + k of the forest array: the slot order is
+// the key order, and the 16 nodes of consecutive cells, which the lanes of a
+// wave touch together, are 17 words apart and so never share an LDS bank.
+// Each entry holds the byte offset (4 x slot) of its parent, so a step of a
+// walk is one load with no index arithmetic.
 template <int NC>
-__device__ __forceinline__ int lds_pos(int key)
+constexpr int kForestSlots = 17 * NC;
+
+__device__ __forceinline__ uint32_t node_off(int key)
 {
-    return (int)(((unsigned)key & 15u) * NC + ((unsigned)key >> 4));
+    return 4u * (uint32_t)(key + (key >> 4));
+}
+
+// Key of the node at byte offset off.
+__device__ __forceinline__ int node_key(uint32_t off)
+{
+    const uint32_t slot = off >> 2, c = slot / 17u;
+    return (int)(slot - c);
+}
+
+// Entry at byte offset off of the forest array, addressed in the LDS
+// address space (a 32-bit offset, no generic-pointer arithmetic).
+typedef __attribute__((address_space(3))) volatile uint32_t lds_word;
+typedef __attribute__((address_space(3))) volatile char lds_byte;
+
+__device__ __forceinline__ lds_word &node(volatile uint32_t *P, uint32_t off)
+{
+    return *(lds_word *)((lds_byte *)P + off);
 }
 
 // Every walk below is capped far above any reachable depth (a forest over n
@@ -38,13 +60,14 @@ __device__ __forceinline__ int lds_pos(int key)
 // never a kernel that does not finish.
 constexpr int kWalkCap = 1 << 22;
 
+// Root of node x (byte offsets), with path splitting.
 template <int NC>
-__device__ __forceinline__ int lds_find(volatile int *P, int x)
+__device__ __forceinline__ uint32_t lds_find(volatile uint32_t *P, uint32_t x)
 {
-    int p = P[lds_pos<NC>(x)];
+    uint32_t p = node(P, x);
     for (int it = 0; p != x && it < 16 * NC; ++it) {
-        const int gp = P[lds_pos<NC>(p)];
-        if (gp != p) P[lds_pos<NC>(x)] = gp;
+        const uint32_t gp = node(P, p);
+        if (gp != p) node(P, x) = gp;
         x = p;
         p = gp;
     }
@@ -55,22 +78,32 @@ __device__ __forceinline__ int lds_find(volatile int *P, int x)
 // atomicMin; if it had been re-parented meanwhile, continue with its new
 // parent.  Parent values only decrease, so every loop ends.
 template <int NC>
-__device__ __forceinline__ void lds_unite(int *P, int a, int b)
+__device__ __forceinline__ void lds_unite(uint32_t *P, uint32_t a, uint32_t b)
 {
-    volatile int *V = P;
+    volatile uint32_t *V = P;
     for (int it = 0; it < 16 * NC; ++it) {
         a = lds_find<NC>(V, a);
         b = lds_find<NC>(V, b);
         if (a == b) return;
         if (a < b) {
-            const int tmp = a;
+            const uint32_t tmp = a;
             a = b;
             b = tmp;
         }
-        const int old = atomicMin(P + lds_pos<NC>(a), b);
+        const uint32_t old = __hip_atomic_fetch_min((__attribute__((address_space(3))) uint32_t *)((lds_byte *)P + a), b,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == a) return;
         a = old;
     }
+}
+
+// Label staging of the flip kernels: the label of local key 16 c + k is kept
+// at k * NC + c, so the lanes of a wave, which own consecutive cells, touch
+// consecutive LDS banks.
+template <int NC>
+__device__ __forceinline__ int lds_pos(int key)
+{
+    return (int)(((unsigned)key & 15u) * NC + ((unsigned)key >> 4));
 }
 
 struct NbrCell {
@@ -365,7 +398,7 @@ constexpr int kUnionsPerCell = 8;
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
                                                 int lcid, bool valid, int cell, int x, int y, int z, uint64_t act,
-                                                const int (&lc)[kNCellCodes], int *P, uint32_t *U,
+                                                const int (&lc)[kNCellCodes], uint32_t *P, uint32_t *U,
                                                 const uint8_t *K4, unsigned *cursor)
 {
     constexpr int NC = TX * TY * TZ;
@@ -380,13 +413,14 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         const uint32_t code = K4[(uint32_t)(act >> (6 * f)) & 63u];
-        const int base = 16 * lcid + 4 * f;
+        const uint32_t base = node_off(16 * lcid + 4 * f);
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) P[(4 * f + mu) * NC + lcid] = base + ((code >> (2 * mu)) & 3);
+        for (int mu = 0; mu < 4; ++mu) node(P, base + 4 * mu) = base + 4 * ((code >> (2 * mu)) & 3);
     }
     if (tid == 0) *cursor = 0;
     __syncthreads();
-    // Down tetrahedra, inside the tile: spanning edges, packed two 16-bit keys.
+    // Down tetrahedra, inside the tile: spanning edges, packed as two 16-bit
+    // forest slots (17 NC < 2^16).
     uint32_t un[12];
     unsigned nun = 0;
     if (valid) {
@@ -407,7 +441,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
                 const int kr = rp == 0 ? k0 : (rp == 1 ? k1 : k2);
                 const int km = mu == 1 ? k1 : (mu == 2 ? k2 : k3);
                 const bool use = rp != mu;
-                un[3 * f + mu - 1] = use ? ((uint32_t)kr << 16 | (uint32_t)km) : 0xFFFFFFFFu;
+                un[3 * f + mu - 1] = use ? (node_off(kr) << 14 | node_off(km) >> 2) : 0xFFFFFFFFu;
                 nun += use;
             }
         }
@@ -418,25 +452,33 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         for (int k = 0; k < 12; ++k) {
             if (un[k] == 0xFFFFFFFFu) continue;
             if (at < (unsigned)kCap) U[at] = un[k];
-            else lds_unite<NC>(P, (int)(un[k] >> 16), (int)(un[k] & 0xFFFFu));
+            else lds_unite<NC>(P, (un[k] >> 14) & ~3u, (un[k] & 0xFFFFu) << 2);
             ++at;
         }
     }
     __syncthreads();
-    const int nlist = min((int)*cursor, kCap);
-    for (int k = tid; k < nlist; k += NC) lds_unite<NC>(P, (int)(U[k] >> 16), (int)(U[k] & 0xFFFFu));
+    // Each thread takes a contiguous run of the list: a cell's unions sit
+    // together in it, so the lanes of a wave work on different cells' roots.
+    {
+        const int nlist = min((int)*cursor, kCap);
+        const int per = (nlist + NC - 1) / NC;
+        const int kb = min(tid * per, nlist), ke = min(kb + per, nlist);
+        for (int k = kb; k < ke; ++k) lds_unite<NC>(P, (U[k] >> 14) & ~3u, (U[k] & 0xFFFFu) << 2);
+    }
     __syncthreads();
-    // Tile-local roots: written to the labels and back into the forest, so
-    // that every node then points straight at its root.
+    // Tile-local roots: written to the labels, and their keys into the
+    // forest entries (read by the crossing-list emission below).
     int r[16];
     if (valid) {
+        const uint32_t base = node_off(16 * lcid);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) r[k] = lds_find<NC>(P, 16 * lcid + k);
+        for (int k = 0; k < 16; ++k) r[k] = node_key(lds_find<NC>(P, base + 4 * k));
     }
     __syncthreads();
     if (valid) {
+        const uint32_t base = node_off(16 * lcid);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) P[lds_pos<NC>(16 * lcid + k)] = r[k];
+        for (int k = 0; k < 16; ++k) node(P, base + 4 * k) = (uint32_t)r[k];
 #pragma unroll
         for (int k = 0; k < 16; ++k) r[k] = ti.global_site(r[k]);
         int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
@@ -456,7 +498,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
                 const SiteRef R = down_vertex(f, mu);
                 if (R.cell == kSelf) return r[R.site] | kTag;
                 const int l = lc[R.cell];
-                if (l >= 0) return ti.global_site(P[lds_pos<NC>(16 * l + R.site)]) | kTag;
+                if (l >= 0) return ti.global_site((int)node(P, node_off(16 * l + R.site))) | kTag;
                 outside = true;
                 return nbr_site(R.cell, R.site, x, y, z, xm, ym, zm, L);
             };
