@@ -55,19 +55,26 @@ __device__ __forceinline__ lds_word &node(volatile uint32_t *P, uint32_t off)
     return *(lds_word *)((lds_byte *)P + off);
 }
 
-// Every walk below is capped far above any reachable depth (a forest over n
-// nodes has depth below n), so a damaged forest can only give a wrong label,
-// never a kernel that does not finish.
+// Every walk in the global forest below is capped far above any reachable
+// depth (a forest over n nodes has depth below n), so a damaged forest can
+// only give a wrong label, never a kernel that does not finish.
 constexpr int kWalkCap = 1 << 22;
 
-// Root of node x (byte offsets), with path splitting.
-template <int NC>
+// In the tile forest a parent's offset is never above its child's (roots
+// hold their own offset): initial parents are the smallest vertex of an up
+// tetrahedron's component, unions lower a root to a smaller one, and path
+// splitting stores ancestors.  Walks therefore step only while the parent is
+// strictly smaller, which bounds them by the forest size whatever the
+// entries hold.
+
+// Root of node x (byte offsets), with path splitting.  The store is
+// unconditional: x is not a root, and any ancestor is a valid parent.
 __device__ __forceinline__ uint32_t lds_find(volatile uint32_t *P, uint32_t x)
 {
     uint32_t p = node(P, x);
-    for (int it = 0; p != x && it < 16 * NC; ++it) {
+    while (p < x) {
         const uint32_t gp = node(P, p);
-        if (gp != p) node(P, x) = gp;
+        node(P, x) = gp;
         x = p;
         p = gp;
     }
@@ -75,15 +82,14 @@ __device__ __forceinline__ uint32_t lds_find(volatile uint32_t *P, uint32_t x)
 }
 
 // Union in an LDS forest: the larger root is lowered to the smaller one with
-// atomicMin; if it had been re-parented meanwhile, continue with its new
-// parent.  Parent values only decrease, so every loop ends.
-template <int NC>
+// atomicMin; if it had been re-parented meanwhile (to a smaller node),
+// continue from there.  The larger root strictly decreases on every retry.
 __device__ __forceinline__ void lds_unite(uint32_t *P, uint32_t a, uint32_t b)
 {
     volatile uint32_t *V = P;
-    for (int it = 0; it < 16 * NC; ++it) {
-        a = lds_find<NC>(V, a);
-        b = lds_find<NC>(V, b);
+    for (;;) {
+        a = lds_find(V, a);
+        b = lds_find(V, b);
         if (a == b) return;
         if (a < b) {
             const uint32_t tmp = a;
@@ -92,7 +98,7 @@ __device__ __forceinline__ void lds_unite(uint32_t *P, uint32_t a, uint32_t b)
         }
         const uint32_t old = __hip_atomic_fetch_min((__attribute__((address_space(3))) uint32_t *)((lds_byte *)P + a), b,
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == a) return;
+        if (old >= a) return;
         a = old;
     }
 }
@@ -452,7 +458,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         for (int k = 0; k < 12; ++k) {
             if (un[k] == 0xFFFFFFFFu) continue;
             if (at < (unsigned)kCap) U[at] = un[k];
-            else lds_unite<NC>(P, (un[k] >> 14) & ~3u, (un[k] & 0xFFFFu) << 2);
+            else lds_unite(P, (un[k] >> 14) & ~3u, (un[k] & 0xFFFFu) << 2);
             ++at;
         }
     }
@@ -463,7 +469,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         const int nlist = min((int)*cursor, kCap);
         const int per = (nlist + NC - 1) / NC;
         const int kb = min(tid * per, nlist), ke = min(kb + per, nlist);
-        for (int k = kb; k < ke; ++k) lds_unite<NC>(P, (U[k] >> 14) & ~3u, (U[k] & 0xFFFFu) << 2);
+        for (int k = kb; k < ke; ++k) lds_unite(P, (U[k] >> 14) & ~3u, (U[k] & 0xFFFFu) << 2);
     }
     __syncthreads();
     // Tile-local roots: written to the labels, and their keys into the
@@ -472,7 +478,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     if (valid) {
         const uint32_t base = node_off(16 * lcid);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) r[k] = node_key(lds_find<NC>(P, base + 4 * k));
+        for (int k = 0; k < 16; ++k) r[k] = node_key(lds_find(P, base + 4 * k));
     }
     __syncthreads();
     if (valid) {
