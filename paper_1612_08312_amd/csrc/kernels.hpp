@@ -54,7 +54,8 @@ struct RepDesc {
     double *dpart;     // FP64 partial sums
     float *axis;       // [4] embedding axis of the current sweep
     DevRecord *ring;   // per-sweep records
-    int *pairs;        // per-tile crossing lists: count, pad, then (name, name) pairs
+    int *pairs;        // per-tile crossing lists: pair count, root count (set by the unite pass), then
+                       // (name, name) pairs, replaced by the distinct local roots when the root count is > 0
     int list_stride;   // ints per tile list (tile shape dependent)
     // constants of the run
     uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24

@@ -559,7 +559,14 @@ enum GlobalPass : int { kPassUnite = 0, kPassMin = 1, kPassStore = 2 };
 // member of smallest link priority (to 22 bits) as representative, and
 // every other member is united with it: the hooks of one tile then target
 // distinct roots.  Pairs beyond the LDS tables are united directly.
-__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, const int2 *list, int n, int tid)
+//
+// The tile's list is then replaced by its distinct local roots (head[1] =
+// their number, the roots from head[2] on), which is all the minimum and
+// store passes need: they skip resolving names again.  head[1] = 0 keeps the
+// pairs (some root did not fit in the table).  A local root that occurs only
+// in pairs whose two names resolve to it is left out: it is never hooked nor
+// hooked under, and its entry (itself) is already its canonical form.
+__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int tid)
 {
     constexpr int H = 1024;           // root slots
     constexpr int kMaxListed = 1024;  // pairs kept in LDS
@@ -567,10 +574,16 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, const int2 *list,
     __shared__ int HP[H];             // LDS parent slot
     __shared__ uint32_t BEST[H];      // per group: (priority high bits | slot) minimum
     __shared__ int16_t PA[kMaxListed], PB[kMaxListed];
+    __shared__ int nroots, missed;
+    const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
     for (int k = tid; k < H; k += kBlock) {
         HK[k] = -1;
         HP[k] = k;
         BEST[k] = 0xFFFFFFFFu;
+    }
+    if (tid == 0) {
+        nroots = 0;
+        missed = 0;
     }
     __syncthreads();
     auto insert = [&](int key) {
@@ -590,12 +603,19 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, const int2 *list,
         const int sa = ra == rb ? -1 : insert(ra), sb = ra == rb ? -1 : insert(rb);
         const bool listed = k < kMaxListed && sa >= 0 && sb >= 0;
         if (!listed && ra != rb) forest_unite(lab, ra, rb);
+        if (ra != rb && (sa < 0 || sb < 0)) missed = 1;
         if (k < kMaxListed) {
             PA[k] = (int16_t)(listed ? sa : -1);
             PB[k] = (int16_t)(listed ? sb : -1);
         }
     }
     __syncthreads();
+    // The pairs are read: overwrite them with the distinct local roots
+    // (at most 2n of them, so they fit where the pairs were).
+    if (!missed) {
+        for (int k = tid; k < H; k += kBlock)
+            if (HK[k] >= 0) head[2 + atomicAdd(&nroots, 1)] = HK[k];
+    }
     auto slot_find = [&](int x) {
         for (int it = 0; it < H; ++it) {
             const int p = HP[x];
@@ -635,6 +655,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, const int2 *list,
         const int rep = (int)(BEST[slot_find(s)] & (uint32_t)(H - 1));
         if (rep != s) forest_unite(lab, HK[s], HK[rep]);
     }
+    if (tid == 0) head[1] = missed ? 0 : nroots;
 }
 
 template <int PASS>
@@ -647,16 +668,24 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     if (c.state[rep]->remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
-    const int *head = d.pairs + (int64_t)tile * d.list_stride;
+    int *head = d.pairs + (int64_t)tile * d.list_stride;
     const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
     const int n = head[0];
     const int tid = threadIdx.x;
     int32_t *lab = d.label;
     if (PASS == kPassUnite) {
-        unite_tile_pairs(lab, list, n, tid);
+        unite_tile_pairs(lab, head, n, tid);
         return;
     }
     if (n == 0) return;
+    const int nroots = head[1];  // > 0: the list holds the tile's distinct local roots
+    if (PASS == kPassStore && nroots > 0) {
+        for (int k = tid; k < nroots; k += kBlock) {
+            const int r = head[2 + k];
+            lab_store(lab, r, encoded_canon(lab, r));
+        }
+        return;
+    }
     for (int k = tid; k < H; k += kBlock) {
         HK[k] = -1;
         if (PASS == kPassMin) HV[k] = INT32_MAX;
@@ -685,11 +714,18 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
         }
         act(key, val);  // table full: act directly
     };
-    for (int k = tid; k < 2 * n; k += kBlock) {
-        const int2 p = list[k >> 1];
-        const int r = name_root(lab, (k & 1) ? p.y : p.x);
-        if (PASS == kPassMin) add(merged_root(lab, r), r);
-        else add(r, r);
+    if (nroots > 0) {
+        for (int k = tid; k < nroots; k += kBlock) {
+            const int r = head[2 + k];
+            add(merged_root(lab, r), r);
+        }
+    } else {
+        for (int k = tid; k < 2 * n; k += kBlock) {
+            const int2 p = list[k >> 1];
+            const int r = name_root(lab, (k & 1) ? p.y : p.x);
+            if (PASS == kPassMin) add(merged_root(lab, r), r);
+            else add(r, r);
+        }
     }
     __syncthreads();
     for (int k = tid; k < H; k += kBlock) {
