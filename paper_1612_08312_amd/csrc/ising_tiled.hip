@@ -53,7 +53,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     const int8_t *__restrict__ s = (const int8_t *)d.spins;
     const int tid = threadIdx.x;
     const int L = d.L;
-    const int lcid = cell_of_thread<TX, TY, TZ>(tid);  // face cells in the first waves
+    const int lcid = tid;  // local cell of the thread
     const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         aligned_count = (int)__popcll(al);
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, x, y, z, act, lc, P, U, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4, &cursor);
     const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - 48) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }

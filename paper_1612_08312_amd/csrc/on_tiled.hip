@@ -72,6 +72,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     constexpr int NC = TX * TY * TZ;
     __shared__ uint32_t P[kForestSlots<NC>];
     __shared__ uint32_t U[kUnionsPerCell * NC];
+    __shared__ uint32_t DA[NC];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
     __shared__ unsigned cursor;
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     const float x0 = d.x0;
     const int tid = threadIdx.x;
     const int L = d.L;
-    const int lcid = cell_of_thread<TX, TY, TZ>(tid);  // face cells in the first waves
+    const int lcid = tid;  // local cell of the thread
     const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
             }
         }
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, x, y, z, act, lc, P, U, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, DA, K4, &cursor);
     const double b = block_sum<double>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }

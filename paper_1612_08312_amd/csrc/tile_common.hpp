@@ -189,12 +189,6 @@ struct TileIdx {
     }
 };
 
-// Only cells on a low face of a tile own bonds that leave the tile.
-__device__ __forceinline__ bool is_face_cell(int lx, int ly, int lz, const RepDesc &d)
-{
-    return (lx == 0 && d.ntx > 1) || (ly == 0 && d.nty > 1) || (lz == 0 && d.ntz > 1);
-}
-
 // ---------------------------------------------------------------- merge ---
 // The global forest lives in the label entries of tile-local roots (the
 // entries of ordinary sites keep pointing at their local root).  Entry
@@ -347,34 +341,42 @@ __device__ __forceinline__ int name_root(const int32_t *lab, int name)
     return (name & kTag) ? (name & kIdxMask) : endpoint_root(lab, name);
 }
 
-// Thread -> local cell order of the tile pass: the cells of the low faces
-// first (in cell order), then the others.  Only low-face cells own crossing
-// bonds, so the emission of crossing pairs runs in the first few waves and
-// the other waves skip it; the low faces are whole rows of cells, so the
-// spin loads of a wave stay row-contiguous.
+// Crossing-pair emission items of a tile shape: one per (low-face cell c,
+// down tetrahedron f) whose tetrahedron can have a vertex outside the tile
+// (f = 0 on every low face, f = 1/2/3 on the face x/y/z = 0), packed as
+// 4 c + f and sorted by f, so the lanes of a wave mostly share f.  Whether a
+// vertex is outside is decided at run time (an axis with a single tile
+// wraps onto itself).
 template <int TX, int TY, int TZ>
-struct FaceFirst {
-    uint16_t c[TX * TY * TZ];
+struct EmitItems {
+    uint16_t v[4 * TX * TY * TZ];
+    int n;
 };
 template <int TX, int TY, int TZ>
-__host__ __device__ constexpr FaceFirst<TX, TY, TZ> make_face_first()
+__host__ __device__ constexpr EmitItems<TX, TY, TZ> make_emit_items()
 {
-    FaceFirst<TX, TY, TZ> t{};
-    int n = 0;
-    for (int pass = 0; pass < 2; ++pass)
+    EmitItems<TX, TY, TZ> t{};
+    t.n = 0;
+    for (int f = 0; f < 4; ++f)
         for (int c = 0; c < TX * TY * TZ; ++c) {
-            const bool face = c % TX == 0 || (c / TX) % TY == 0 || c / (TX * TY) == 0;
-            if (face == (pass == 0)) t.c[n++] = (uint16_t)c;
+            const bool fx = c % TX == 0, fy = (c / TX) % TY == 0, fz = c / (TX * TY) == 0;
+            const bool use = f == 0 ? (fx || fy || fz) : (f == 1 ? fx : (f == 2 ? fy : fz));
+            if (use) t.v[t.n++] = (uint16_t)(4 * c + f);
         }
     return t;
 }
 template <int TX, int TY, int TZ>
-__constant__ FaceFirst<TX, TY, TZ> kFaceFirst = make_face_first<TX, TY, TZ>();
+__constant__ EmitItems<TX, TY, TZ> kEmitItems = make_emit_items<TX, TY, TZ>();
 
-template <int TX, int TY, int TZ>
-__device__ __forceinline__ int cell_of_thread(int tid)
+// Vertex mu of down tetrahedron f as (cell code << 4 | site), byte 4 f + mu.
+__host__ __device__ constexpr uint64_t down_vertex_bytes(int half)
 {
-    return kFaceFirst<TX, TY, TZ>.c[tid];
+    uint64_t w = 0;
+    for (int k = 0; k < 8; ++k) {
+        const SiteRef R = down_vertex(2 * half + k / 4, k % 4);
+        w |= (uint64_t)(R.cell << 4 | R.site) << (8 * k);
+    }
+    return w;
 }
 
 // ------------------------------------------------------ tile components ---
@@ -384,9 +386,10 @@ constexpr int kUnionsPerCell = 8;
 
 // Second half of both models' tile pass (every thread of the block calls
 // it; `act` is 0 for threads without a cell, lc[] holds the local index of
-// each neighbour cell of the thread's cell, or -1 outside the tile):
-// the components of the tile's sites from the active bonds of its cells,
-// written as every site's tile-local root, and the tile's crossing list.
+// each neighbour cell of the thread's cell, or -1 outside the tile; DA is
+// LDS for one word per cell): the components of the tile's sites from the
+// active bonds of its cells, written as every site's tile-local root, and
+// the tile's crossing list.
 //
 // Inside the tile, each down tetrahedron contributes the spanning edges of
 // the components of its active bonds whose two ends lie in the tile (at most
@@ -395,16 +398,17 @@ constexpr int kUnionsPerCell = 8;
 //
 // Every site is a vertex of exactly one down tetrahedron, owned by one cell,
 // so the crossing bonds of different cells never join the same pair of
-// sites.  For each down tetrahedron with a vertex outside the tile, the
-// owning thread names each vertex by its tile-local root with the tag bit
-// set (inside) or by its site index (outside) and emits, per component of
-// the tetrahedron's active bonds, the edges from the component's smallest
-// vertex to the others whose name differs: at most 3 pairs per tetrahedron,
-// none repeated.
+// sites.  For each down tetrahedron with a vertex outside the tile, each
+// vertex is named by its tile-local root with the tag bit set (inside) or
+// by its site index (outside), and per component of the tetrahedron's
+// active bonds the edges from the component's smallest vertex to the others
+// whose name differs are emitted: at most 3 pairs per tetrahedron, none
+// repeated.  These tetrahedra belong to the cells of the low faces; they
+// are handed out to all threads as a table of (cell, tetrahedron) items.
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
-                                                int lcid, bool valid, int cell, int x, int y, int z, uint64_t act,
-                                                const int (&lc)[kNCellCodes], uint32_t *P, uint32_t *U,
+                                                int lcid, bool valid, int cell, uint64_t act,
+                                                const int (&lc)[kNCellCodes], uint32_t *P, uint32_t *U, uint32_t *DA,
                                                 const uint8_t *K4, unsigned *cursor)
 {
     constexpr int NC = TX * TY * TZ;
@@ -472,8 +476,9 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         for (int k = kb; k < ke; ++k) lds_unite(P, (U[k] >> 14) & ~3u, (U[k] & 0xFFFFu) << 2);
     }
     __syncthreads();
-    // Tile-local roots: written to the labels, and their keys into the
-    // forest entries (read by the crossing-list emission below).
+    // Tile-local roots of the thread's sites, as global site indices: into
+    // the labels, and into the forest entries, where the emission below
+    // reads the root of any site of the tile.
     int r[16];
     if (valid) {
         const uint32_t base = node_off(16 * lcid);
@@ -484,55 +489,65 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     if (valid) {
         const uint32_t base = node_off(16 * lcid);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) node(P, base + 4 * k) = (uint32_t)r[k];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) r[k] = ti.global_site(r[k]);
+        for (int k = 0; k < 16; ++k) {
+            r[k] = ti.global_site(r[k]);
+            node(P, base + 4 * k) = (uint32_t)r[k];
+        }
         int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
     }
+    DA[lcid] = (uint32_t)(act >> 24);  // active bonds of the cell's down tetrahedra
     if (tid == 0) *cursor = 0;
     __syncthreads();
-    int2 pr[12];
-    unsigned npair = 0;
-    if (valid) {
-        const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
-        if (is_face_cell(lx, ly, lz, d)) {
-            const int L = d.L;
-            const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
-            auto vertex_id = [&](int f, int mu, bool &outside) {
-                const SiteRef R = down_vertex(f, mu);
-                if (R.cell == kSelf) return r[R.site] | kTag;
-                const int l = lc[R.cell];
-                if (l >= 0) return ti.global_site((int)node(P, node_off(16 * l + R.site))) | kTag;
+    // Crossing pairs, one item (cell, down tetrahedron) at a time, spread
+    // over all threads.
+    const int L = d.L;
+    int2 *list = reinterpret_cast<int2 *>(d.pairs + (int64_t)tile * d.list_stride) + 1;
+    constexpr uint64_t kVert0 = down_vertex_bytes(0), kVert1 = down_vertex_bytes(1);
+    constexpr uint32_t kLowerAxes = 0u | 1u << 3 | 2u << 6 | 4u << 9 | 6u << 12 | 5u << 15 | 3u << 18;
+    for (int j = tid; j < kEmitItems<TX, TY, TZ>.n; j += NC) {
+        const int item = kEmitItems<TX, TY, TZ>.v[j];
+        const int c = item >> 2, f = item & 3;
+        const int ix = c % TX, iy = (c / TX) % TY, iz = c / (TX * TY);
+        const int cx = ti.bx * TX + ix, cy = ti.by * TY + iy, cz = ti.bz * TZ + iz;
+        if (cx >= L || cy >= L || cz >= L) continue;
+        const int xm = cx == 0 ? L - 1 : cx - 1, ym = cy == 0 ? L - 1 : cy - 1, zm = cz == 0 ? L - 1 : cz - 1;
+        const uint64_t vb = (f < 2) ? kVert0 : kVert1;
+        bool outside = false;
+        int id[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const uint32_t v = (uint32_t)(vb >> (8 * (4 * (f & 1) + mu))) & 0xFFu;
+            const int code = (int)(v >> 4), site = (int)(v & 15u);
+            const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
+            const int nx = (mk & 1u) ? xm : cx, ny = (mk & 2u) ? ym : cy, nz = (mk & 4u) ? zm : cz;
+            const NbrCell nb = ti.at(nx, ny, nz);
+            if (nb.lcell >= 0) {
+                id[mu] = (int)node(P, node_off(16 * nb.lcell + site)) | kTag;
+            } else {
+                id[mu] = 16 * nb.gcell + site;
                 outside = true;
-                return nbr_site(R.cell, R.site, x, y, z, xm, ym, zm, L);
-            };
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                bool outside = false;
-                const int id0 = vertex_id(f, 0, outside), id1 = vertex_id(f, 1, outside);
-                const int id2 = vertex_id(f, 2, outside), id3 = vertex_id(f, 3, outside);
-                // 0xE4: four singletons
-                const uint32_t code = outside ? K4[(uint32_t)(act >> (24 + 6 * f)) & 63u] : 0xE4u;
-#pragma unroll
-                for (int mu = 1; mu < 4; ++mu) {
-                    const int rp = (code >> (2 * mu)) & 3;
-                    const int rid = rp == 0 ? id0 : (rp == 1 ? id1 : id2);
-                    const int own = mu == 1 ? id1 : (mu == 2 ? id2 : id3);
-                    const bool emit = rp != mu && rid != own;
-                    pr[3 * f + mu - 1] = emit ? make_int2(rid, own) : make_int2(-1, -1);
-                    npair += emit;
-                }
             }
         }
-    }
-    if (npair) {
-        int2 *list = reinterpret_cast<int2 *>(d.pairs + (int64_t)tile * d.list_stride) + 1;
-        unsigned at = atomicAdd(cursor, npair);
+        if (!outside) continue;
+        const uint32_t code = K4[(DA[c] >> (6 * f)) & 63u];
+        int2 pr[3];
+        unsigned npair = 0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k)
-            if (pr[k].x != -1) list[at++] = pr[k];
+        for (int mu = 1; mu < 4; ++mu) {
+            const int rp = (code >> (2 * mu)) & 3;
+            const int rid = rp == 0 ? id[0] : (rp == 1 ? id[1] : id[2]);
+            const bool emit = rp != mu && rid != id[mu];
+            pr[mu - 1] = emit ? make_int2(rid, id[mu]) : make_int2(-1, -1);
+            npair += emit;
+        }
+        if (npair) {
+            unsigned at = atomicAdd(cursor, npair);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (pr[k].x != -1) list[at++] = pr[k];
+        }
     }
     __syncthreads();
     if (tid == 0) d.pairs[(int64_t)tile * d.list_stride] = (int)*cursor;
