@@ -1,4 +1,5 @@
-// Small device helpers: deterministic block reductions.
+// Small device helpers: lattice index products, deterministic block
+// reductions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,6 +8,14 @@
 namespace pyro {
 
 constexpr int kWave = 64;
+
+// Product of non-negative a, b below 2^24 (every lattice index product:
+// L <= 406, so cell indices stay below 2^27) on the full-rate 24-bit
+// multiplier; a 32-bit integer multiply is a quarter-rate instruction.
+__device__ __forceinline__ int mul24(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
+
+// Index (z L + y) L + x of cell (x, y, z).
+__device__ __forceinline__ int cell_index(int x, int y, int z, int L) { return mul24(mul24(z, L) + y, L) + x; }
 
 // Deterministic sum over a block (blockDim.x multiple of 64, at most 1024):
 // fixed shuffle tree inside each wave, then the wave sums in wave order.

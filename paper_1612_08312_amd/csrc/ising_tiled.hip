@@ -57,7 +57,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
-    const int cell = (z * L + y) * L + x;
+    const int cell = cell_index(x, y, z, L);
 
     if (tid < 64) {
         constexpr K4Table k4 = make_k4();
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
-    const int cell = (z * L + y) * L + x;
+    const int cell = cell_index(x, y, z, L);
     int lab[16];
     if (valid) {
         const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
-    const int cell = (z * L + y) * L + x;
+    const int cell = cell_index(x, y, z, L);
     if (tid < 64) {
         constexpr K4Table k4 = make_k4();
         K4[tid] = k4.v[tid];
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = x < L && y < L && z < L;
-    const int cell = (z * L + y) * L + x;
+    const int cell = cell_index(x, y, z, L);
     const int64_t N = d.N;
     float *s = (float *)d.spins;
     int lab[16];

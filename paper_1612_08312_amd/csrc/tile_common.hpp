@@ -38,10 +38,11 @@ __device__ __forceinline__ uint32_t node_off(int key)
     return 4u * (uint32_t)(key + (key >> 4));
 }
 
-// Key of the node at byte offset off.
+// Key of the node at byte offset off: slot - slot / 17, the quotient by a
+// 24-bit multiply and shift (exact for every slot below 2^16).
 __device__ __forceinline__ int node_key(uint32_t off)
 {
-    const uint32_t slot = off >> 2, c = slot / 17u;
+    const uint32_t slot = off >> 2, c = __umul24(slot, 61681u) >> 20;
     return (int)(slot - c);
 }
 
@@ -122,8 +123,8 @@ struct NbrCell {
 __device__ __forceinline__ int small_div(int a, int b, float inv_b)
 {
     int q = (int)((float)a * inv_b);
-    if (q * b > a) --q;
-    else if ((q + 1) * b <= a) ++q;
+    if (mul24(q, b) > a) --q;
+    else if (mul24(q + 1, b) <= a) ++q;
     return q;
 }
 
@@ -149,7 +150,7 @@ struct TileIdx {
     __device__ __forceinline__ NbrCell at(int x, int y, int z) const
     {
         NbrCell c;
-        c.gcell = (z * L + y) * L + x;
+        c.gcell = cell_index(x, y, z, L);
         const int tx = x - bx * TX, ty = y - by * TY, tz = z - bz * TZ;
         const bool in = (unsigned)tx < (unsigned)TX && (unsigned)ty < (unsigned)TY && (unsigned)tz < (unsigned)TZ;
         c.lcell = in ? (tz * TY + ty) * TX + tx : -1;
@@ -160,7 +161,7 @@ struct TileIdx {
     {
         const unsigned lc = (unsigned)l >> 4;  // keys are non-negative; unsigned keeps % and / to masks and shifts
         const int lx = (int)(lc % TX), ly = (int)((lc / TX) % TY), lz = (int)(lc / (TX * TY));
-        return 16 * (base + (lz * L + ly) * L + lx) + (l & 15);
+        return 16 * (base + cell_index(lx, ly, lz, L)) + (l & 15);
     }
     // Local key 16 c + k of a global site index known to lie in this tile
     // (offsets from the tile's first cell are below TZ L^2 < 2^24).
@@ -169,9 +170,9 @@ struct TileIdx {
         const int off = (site >> 4) - base;
         const int LL = L * L;
         const int lz = small_div(off, LL, inv_LL);
-        const int rem = off - lz * LL;
+        const int rem = off - mul24(lz, LL);
         const int ly = small_div(rem, L, inv_L);
-        const int lx = rem - ly * L;
+        const int lx = rem - mul24(ly, L);
         return 16 * ((lz * TY + ly) * TX + lx) + (site & 15);
     }
     // The seven cells the bonds of cell (x, y, z) touch (periodic wrap).
@@ -322,7 +323,7 @@ __device__ __forceinline__ int nbr_site(int code, int site, int x, int y, int z,
     constexpr uint32_t kLowerAxes = 0u | 1u << 3 | 2u << 6 | 4u << 9 | 6u << 12 | 5u << 15 | 3u << 18;
     const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
     const int cx = (mk & 1u) ? xm : x, cy = (mk & 2u) ? ym : y, cz = (mk & 4u) ? zm : z;
-    return 16 * ((cz * L + cy) * L + cx) + site;
+    return 16 * cell_index(cx, cy, cz, L) + site;
 }
 
 // Local root of site e (a plain, possibly stale load is exact: the entry of
