@@ -54,7 +54,7 @@ def bytes_per_site(shape):
 # each scaled by the same counter's reading for the probe's 256 MiB copy.
 # Valid only for the kernel sources they were taken with (fingerprint).
 MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
-    "local": ("90b45709fb09d305", 217001622),  # profiles/k_local_ising_L128_traffic.md
+    "local": ("b86238b36a9ad38f", 216922650),  # profiles/k_local_ising_L128_traffic.md
 }
 
 
