@@ -40,7 +40,6 @@ def bytes_per_site(shape):
     return {
         "local": 1.0 + 4.0,            # read spins, write tile-local roots
         "unite": 0.0,                  # forest walks over the crossing lists (data dependent)
-        "canon_min": 0.0,              # idem
         "canon_store": 0.0,            # idem
         "coins": 1.0 / 8,              # write one flip coin per site
         "flip": 4.0 + 1.0 + 1.0 + 1.0 / 8,  # read labels, read and write spins, read coins

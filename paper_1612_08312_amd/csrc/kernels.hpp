@@ -101,7 +101,6 @@ enum KernelId : int {
     kKFinalize,
     kKAxis,      // O(n) axis
     kKCompress,  // forest store pass ("canon_store")
-    kKCanonMin,  // forest minimum pass
     kNumKernels
 };
 const char *kernel_name(int id);

@@ -196,39 +196,30 @@ struct TileIdx {
 // encodings of a local root r:
 //   r                   r is a root of the merged forest
 //   kTag | p            r was hooked under p
-//   kCanonBase + c      r is a merged root after the minimum pass: c is the
-//                       smallest site index of r's cluster
+//   kCanonBase + c      written by the store pass: c is the smallest site
+//                       index of r's cluster
 // Site indices are below 2^30 (L <= 406), so the three forms are distinct and
 // the local root of any site is decodable at any time, even while other
 // threads hook roots or store canonical labels: an entry that is negative,
 // tagged or equal to the site's own index names the site itself.
 //
-// Roots are linked by a fixed pseudo-random priority (a bijective hash of
-// the site index): a root is always hooked under the root of smaller
-// priority, so trees stay shallow (expected logarithmic depth) even when one
-// cluster spans every tile, whereas linking by index builds chains through
-// the tiles.  The smallest index of each merged cluster is then stored in
-// its tree root by the minimum pass and copied into every local root of the
-// cluster by the store pass.
+// A root is always hooked under the smaller of the two roots, so every tree
+// root is the smallest local root of its tree, i.e. the smallest site of
+// its cluster, and the store pass only has to copy it into every local root
+// of the cluster.  The unite pass hooks each tile's group of roots under
+// its smallest member in one step, which keeps the trees shallow.
 constexpr int kTag = 1 << 30;
 constexpr int kIdxMask = kTag - 1;
 constexpr int kCanonBase = INT32_MIN;  // canonical index c is stored as kCanonBase + c
-
-__device__ __forceinline__ uint32_t link_priority(int x)
-{
-    const uint32_t h = (uint32_t)x * 0x9E3779B1u;
-    return h ^ (h >> 16);
-}
 
 // Forest entries are read and written with relaxed workgroup-scope atomics,
 // which the caches may serve stale within a launch (agent-scope loads would
 // go past the per-XCD L2 on every step of every walk).  A stale value is an
 // older value of the same entry, and every value an entry ever holds is an
 // ancestor of the node in the final forest (hooks link roots, shortcuts
-// store ancestors, minimum and store passes write only encodings that end a
-// walk), so a stale walk is only longer, never wrong; the updates that
-// decide the forest (hook CAS, atomicMin) are device-wide atomics and
-// return the current value.  Launch boundaries make all writes visible.
+// store ancestors, the store pass writes only encodings that end a walk),
+// so a stale walk is only longer, never wrong; the updates that decide the
+// forest (hook CAS) are device-wide atomics and return the current value.  Launch boundaries make all writes visible.
 __device__ __forceinline__ int lab_load(const int32_t *lab, int x)
 {
     return __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -254,16 +245,16 @@ __device__ __forceinline__ int forest_find(int32_t *lab, int x)
     return x;
 }
 
-// Union of the trees of local roots a and b: at two roots the one of larger
-// priority is hooked under the other by CAS; a lost CAS continues from the
-// value it returned.
+// Union of the trees of local roots a and b: at two roots the larger is
+// hooked under the smaller by CAS; a lost CAS continues from the value it
+// returned.
 __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
 {
     for (int it = 0; it < kWalkCap; ++it) {
         a = forest_find(lab, a);
         b = forest_find(lab, b);
         if (a == b) return;
-        if (link_priority(a) < link_priority(b)) {
+        if (a < b) {
             const int tmp = a;
             a = b;
             b = tmp;
@@ -274,21 +265,10 @@ __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
     }
 }
 
-// Root of local root x in the merged forest (no hooking runs any more); a
-// root holds itself, or an encoded minimum once the minimum pass reached it.
-__device__ __forceinline__ int merged_root(const int32_t *lab, int x)
-{
-    for (int it = 0; it < kWalkCap; ++it) {
-        const int v = lab_load(lab, x);
-        if (v == x || v < 0) return x;
-        x = v & kIdxMask;
-    }
-    return x;
-}
-
-// Encoded canonical index of the cluster of local root x (after the
-// minimum pass): the walk stops at the first negative value, the tree
-// root's encoded minimum or one the store pass has already copied down.
+// Encoded canonical index of the cluster of local root x (after the unite
+// pass): the walk stops at the tree root, whose index is the cluster's
+// smallest site, or at the first encoding the store pass has already
+// written on the way.
 __device__ __forceinline__ int encoded_canon(const int32_t *lab, int x)
 {
     for (int it = 0; it < kWalkCap; ++it) {
@@ -556,29 +536,24 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 
 // ------------------------------------------------------- forest passes ---
 // Passes over the tiles' crossing lists, one workgroup of kBlock threads per
-// tile (three launches, each seeing the previous one complete):
+// tile (two launches, the second seeing the first complete):
 //   kPassUnite  unite the local roots of the two names of every pair;
-//   kPassMin    lower each merged root to the encoding of the smallest local
-//               root of its cluster (= the smallest site of the cluster);
-//               the workgroup first reduces per merged root in LDS, so a
-//               root shared by every pair (one giant cluster) receives one
-//               atomic per tile instead of one per pair;
-//   kPassStore  store that encoding in every local root of the list (walks
-//               stop at the first stored encoding, so they shorten as the
-//               pass proceeds).
-enum GlobalPass : int { kPassUnite = 0, kPassMin = 1, kPassStore = 2 };
+//   kPassStore  store the encoded root of its tree (the cluster's smallest
+//               site) in every local root of the list (walks stop at the
+//               first stored encoding, so they shorten as the pass proceeds).
+enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 
 // Unite pass of one tile (kBlock threads).  The pairs of a tile mostly share
 // a few local roots, so hooking them one by one makes the tile's threads
 // race for the same roots.  Instead, the distinct local roots of the list
-// are grouped by the list's pairs in an LDS union-find, each group picks the
-// member of smallest link priority (to 22 bits) as representative, and
-// every other member is united with it: the hooks of one tile then target
-// distinct roots.  Pairs beyond the LDS tables are united directly.
+// are grouped by the list's pairs in an LDS union-find, and every member of
+// a group is united with the group's smallest member: the hooks of one tile
+// then target distinct roots.  Pairs beyond the LDS tables are united
+// directly.
 //
 // The tile's list is then replaced by its distinct local roots (head[1] =
-// their number, the roots from head[2] on), which is all the minimum and
-// store passes need: they skip resolving names again.  head[1] = 0 keeps the
+// their number, the roots from head[2] on), which is all the store pass
+// needs: it skips resolving names again.  head[1] = 0 keeps the
 // pairs (some root did not fit in the table).  A local root that occurs only
 // in pairs whose two names resolve to it is left out: it is never hooked nor
 // hooked under, and its entry (itself) is already its canonical form.
@@ -588,7 +563,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     constexpr int kMaxListed = 1024;  // pairs kept in LDS
     __shared__ int HK[H];             // local root of the slot, -1 if free
     __shared__ int HP[H];             // LDS parent slot
-    __shared__ uint32_t BEST[H];      // per group: (priority high bits | slot) minimum
+    __shared__ uint32_t BEST[H];      // per group: smallest member
     __shared__ int16_t PA[kMaxListed], PB[kMaxListed];
     __shared__ int nroots, missed;
     const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
@@ -663,13 +638,13 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     __syncthreads();
     for (int s = tid; s < H; s += kBlock) {
         if (HK[s] < 0) continue;
-        atomicMin(&BEST[slot_find(s)], (link_priority(HK[s]) & ~(uint32_t)(H - 1)) | (uint32_t)s);
+        atomicMin(&BEST[slot_find(s)], (uint32_t)HK[s]);
     }
     __syncthreads();
     for (int s = tid; s < H; s += kBlock) {
         if (HK[s] < 0) continue;
-        const int rep = (int)(BEST[slot_find(s)] & (uint32_t)(H - 1));
-        if (rep != s) forest_unite(lab, HK[s], HK[rep]);
+        const int rep = (int)BEST[slot_find(s)];
+        if (rep != HK[s]) forest_unite(lab, HK[s], rep);
     }
     if (tid == 0) head[1] = missed ? 0 : nroots;
 }
@@ -679,7 +654,6 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
 {
     constexpr int H = 1024;
     __shared__ int HK[PASS == kPassUnite ? 1 : H];
-    __shared__ int HV[PASS == kPassMin ? H : 1];
     const int rep = c.tile_rep[blockIdx.x];
     if (c.state[rep]->remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
@@ -695,59 +669,36 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     }
     if (n == 0) return;
     const int nroots = head[1];  // > 0: the list holds the tile's distinct local roots
-    if (PASS == kPassStore && nroots > 0) {
+    if (nroots > 0) {
         for (int k = tid; k < nroots; k += kBlock) {
             const int r = head[2 + k];
             lab_store(lab, r, encoded_canon(lab, r));
         }
         return;
     }
-    for (int k = tid; k < H; k += kBlock) {
-        HK[k] = -1;
-        if (PASS == kPassMin) HV[k] = INT32_MAX;
-    }
+    // The list kept its pairs: store once per distinct local root, found
+    // through an LDS hash table (a full table stores directly).
+    for (int k = tid; k < H; k += kBlock) HK[k] = -1;
     __syncthreads();
-    // key: merged root (min pass) or local root (store pass); value: the
-    // smallest local root seen under that key (min pass)
-    auto act = [&](int key, int val) {
-        if (PASS == kPassMin) {
-            if (lab_load(lab, key) > kCanonBase + val) atomicMin(lab + key, kCanonBase + val);
-        } else {
-            lab_store(lab, key, encoded_canon(lab, key));
-        }
-    };
-    auto add = [&](int key, int val) {
+    auto add = [&](int key) {
         uint32_t h = (uint32_t)key * 0x9E3779B1u;
         h ^= h >> 15;
         for (int probe = 0; probe < 32; ++probe) {
             const int slot = (int)((h + (uint32_t)probe) & (H - 1));
             int prev = HK[slot];
             if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
-            if (prev == -1 || prev == key) {
-                if (PASS == kPassMin) atomicMin(&HV[slot], val);
-                return;
-            }
+            if (prev == -1 || prev == key) return;
         }
-        act(key, val);  // table full: act directly
+        lab_store(lab, key, encoded_canon(lab, key));
     };
-    if (nroots > 0) {
-        for (int k = tid; k < nroots; k += kBlock) {
-            const int r = head[2 + k];
-            add(merged_root(lab, r), r);
-        }
-    } else {
-        for (int k = tid; k < 2 * n; k += kBlock) {
-            const int2 p = list[k >> 1];
-            const int r = name_root(lab, (k & 1) ? p.y : p.x);
-            if (PASS == kPassMin) add(merged_root(lab, r), r);
-            else add(r, r);
-        }
+    for (int k = tid; k < 2 * n; k += kBlock) {
+        const int2 p = list[k >> 1];
+        add(name_root(lab, (k & 1) ? p.y : p.x));
     }
     __syncthreads();
     for (int k = tid; k < H; k += kBlock) {
         const int key = HK[k];
-        if (key < 0) continue;
-        act(key, PASS == kPassMin ? HV[k] : key);
+        if (key >= 0) lab_store(lab, key, encoded_canon(lab, key));
     }
 }
 
