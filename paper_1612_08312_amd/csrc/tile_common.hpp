@@ -245,19 +245,26 @@ __device__ __forceinline__ int forest_find(int32_t *lab, int x)
     return x;
 }
 
-// Union of the trees of local roots a and b: at two roots the larger is
-// hooked under the smaller by CAS; a lost CAS continues from the value it
-// returned.
+// Union of the trees of local roots a and b.  Every parent is smaller than
+// its child (hooks put the larger root under a smaller node, shortcuts store
+// ancestors), so a root may be hooked under any node smaller than itself:
+// that node cannot lie in the root's own tree.  Hence a's root is walked
+// first and, when it is larger than b, hooked under b by CAS without walking
+// b; otherwise b's root is walked and the larger of the two roots is hooked
+// under the smaller.  A lost CAS continues from the value it returned.
 __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
 {
     for (int it = 0; it < kWalkCap; ++it) {
         a = forest_find(lab, a);
-        b = forest_find(lab, b);
         if (a == b) return;
         if (a < b) {
-            const int tmp = a;
-            a = b;
-            b = tmp;
+            b = forest_find(lab, b);
+            if (a == b) return;
+            if (a < b) {
+                const int tmp = a;
+                a = b;
+                b = tmp;
+            }
         }
         const int old = atomicCAS(lab + a, a, kTag | b);
         if (old == a) return;
