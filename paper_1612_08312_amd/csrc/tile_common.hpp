@@ -558,26 +558,31 @@ enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 // then target distinct roots.  Pairs beyond the LDS tables are united
 // directly.
 //
-// The tile's list is then replaced by its distinct local roots (head[1] =
-// their number, the roots from head[2] on), which is all the store pass
-// needs: it skips resolving names again.  head[1] = 0 keeps the
-// pairs (some root did not fit in the table).  A local root that occurs only
-// in pairs whose two names resolve to it is left out: it is never hooked nor
+// The tile's list is then replaced by its distinct local roots, which is all
+// the store pass needs: it skips resolving names again.  With room for it
+// (list_stride >= 2 + 2 H), head[1] = -m and the m roots from head[2] on are
+// followed, from head[2 + H] on, by the list position of each root's group
+// representative, so the store pass walks once per group.  Otherwise
+// head[1] = m and only the roots are written.  head[1] = 0 keeps the pairs
+// (some root did not fit in the table).  A local root that occurs only in
+// pairs whose two names resolve to it is left out: it is never hooked nor
 // hooked under, and its entry (itself) is already its canonical form.
-__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int tid)
+constexpr int kTileRoots = 1024;  // LDS root table of the unite pass
+
+__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid)
 {
-    constexpr int H = 1024;           // root slots
+    constexpr int H = kTileRoots;     // root slots
     constexpr int kMaxListed = 1024;  // pairs kept in LDS
     __shared__ int HK[H];             // local root of the slot, -1 if free
     __shared__ int HP[H];             // LDS parent slot
-    __shared__ uint32_t BEST[H];      // per group: smallest member
+    __shared__ uint64_t BEST[H];      // per group: smallest member << 10 | its slot
     __shared__ int16_t PA[kMaxListed], PB[kMaxListed];
     __shared__ int nroots, missed;
     const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
     for (int k = tid; k < H; k += kBlock) {
         HK[k] = -1;
         HP[k] = k;
-        BEST[k] = 0xFFFFFFFFu;
+        BEST[k] = ~0ull;
     }
     if (tid == 0) {
         nroots = 0;
@@ -608,12 +613,6 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         }
     }
     __syncthreads();
-    // The pairs are read: overwrite them with the distinct local roots
-    // (at most 2n of them, so they fit where the pairs were).
-    if (!missed) {
-        for (int k = tid; k < H; k += kBlock)
-            if (HK[k] >= 0) head[2 + atomicAdd(&nroots, 1)] = HK[k];
-    }
     auto slot_find = [&](int x) {
         for (int it = 0; it < H; ++it) {
             const int p = HP[x];
@@ -645,21 +644,35 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     __syncthreads();
     for (int s = tid; s < H; s += kBlock) {
         if (HK[s] < 0) continue;
-        atomicMin(&BEST[slot_find(s)], (uint32_t)HK[s]);
+        atomicMin(&BEST[slot_find(s)], (uint64_t)HK[s] << 10 | (uint64_t)s);
+    }
+    __syncthreads();
+    // The pairs are read: overwrite them with the distinct local roots (at
+    // most 2n of them, so they fit where the pairs were); PA now holds each
+    // slot's list position.
+    const bool with_reps = list_stride >= 2 + 2 * H;
+    if (!missed) {
+        for (int s = tid; s < H; s += kBlock) {
+            if (HK[s] < 0) continue;
+            const int j = atomicAdd(&nroots, 1);
+            PA[s] = (int16_t)j;
+            head[2 + j] = HK[s];
+        }
     }
     __syncthreads();
     for (int s = tid; s < H; s += kBlock) {
         if (HK[s] < 0) continue;
-        const int rep = (int)BEST[slot_find(s)];
-        if (rep != HK[s]) forest_unite(lab, HK[s], rep);
+        const int rs = (int)(BEST[slot_find(s)] & (uint64_t)(H - 1));
+        if (!missed && with_reps) head[2 + H + PA[s]] = PA[rs];
+        if (rs != s) forest_unite(lab, HK[s], HK[rs]);
     }
-    if (tid == 0) head[1] = missed ? 0 : nroots;
+    if (tid == 0) head[1] = missed ? 0 : (with_reps ? -nroots : nroots);
 }
 
 template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
 {
-    constexpr int H = 1024;
+    constexpr int H = kTileRoots;
     __shared__ int HK[PASS == kPassUnite ? 1 : H];
     const int rep = c.tile_rep[blockIdx.x];
     if (c.state[rep]->remaining <= 0) return;
@@ -671,11 +684,27 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     const int tid = threadIdx.x;
     int32_t *lab = d.label;
     if (PASS == kPassUnite) {
-        unite_tile_pairs(lab, head, n, tid);
+        unite_tile_pairs(lab, head, n, d.list_stride, tid);
         return;
     }
     if (n == 0) return;
-    const int nroots = head[1];  // > 0: the list holds the tile's distinct local roots
+    const int nroots = head[1];  // != 0: the list holds the tile's distinct local roots
+    if (nroots < 0) {
+        // with group representatives: one walk per group, then plain stores
+        const int m = -nroots;
+        const int *rp = head + 2 + H;
+        for (int k = tid; k < m; k += kBlock) {
+            if (rp[k] != k) continue;
+            const int r = head[2 + k];
+            const int e = encoded_canon(lab, r);
+            HK[k] = e;
+            lab_store(lab, r, e);
+        }
+        __syncthreads();
+        for (int k = tid; k < m; k += kBlock)
+            if (rp[k] != k) lab_store(lab, head[2 + k], HK[rp[k]]);
+        return;
+    }
     if (nroots > 0) {
         for (int k = tid; k < nroots; k += kBlock) {
             const int r = head[2 + k];
