@@ -400,6 +400,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
                                                 const uint8_t *K4, unsigned *cursor)
 {
     constexpr int NC = TX * TY * TZ;
+    static_assert(NC % 64 == 0, "tiles are whole waves");
     constexpr int kCap = kUnionsPerCell * NC;
     // local key of vertex mu of down tetrahedron f (-1 when outside the tile)
     auto vkey = [&](int f, int mu) {
@@ -486,59 +487,79 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         for (int q = 0; q < 4; ++q) out[q] = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
     }
     DA[lcid] = (uint32_t)(act >> 24);  // active bonds of the cell's down tetrahedra
-    if (tid == 0) *cursor = 0;
     __syncthreads();
-    // Crossing pairs, one item (cell, down tetrahedron) at a time, spread
-    // over all threads.
+    // Crossing pairs, one item (cell, down tetrahedron) per thread and round.
+    // Each round places its pairs in item order: a lane's offset is the
+    // number of pairs of the lanes below it (two ballots of the 0..3 pair
+    // count), plus the totals of the lower waves, kept in U (free by now).
     const int L = d.L;
     int2 *list = reinterpret_cast<int2 *>(d.pairs + (int64_t)tile * d.list_stride) + 1;
     constexpr uint64_t kVert0 = down_vertex_bytes(0), kVert1 = down_vertex_bytes(1);
     constexpr uint32_t kLowerAxes = 0u | 1u << 3 | 2u << 6 | 4u << 9 | 6u << 12 | 5u << 15 | 3u << 18;
-    for (int j = tid; j < kEmitItems<TX, TY, TZ>.n; j += NC) {
-        const int item = kEmitItems<TX, TY, TZ>.v[j];
-        const int c = item >> 2, f = item & 3;
-        const int ix = c % TX, iy = (c / TX) % TY, iz = c / (TX * TY);
-        const int cx = ti.bx * TX + ix, cy = ti.by * TY + iy, cz = ti.bz * TZ + iz;
-        if (cx >= L || cy >= L || cz >= L) continue;
-        const int xm = cx == 0 ? L - 1 : cx - 1, ym = cy == 0 ? L - 1 : cy - 1, zm = cz == 0 ? L - 1 : cz - 1;
-        const uint64_t vb = (f < 2) ? kVert0 : kVert1;
-        bool outside = false;
-        int id[4];
+    constexpr int kItems = make_emit_items<TX, TY, TZ>().n;
+    int placed = 0;  // pairs listed so far (the same in every thread)
+    for (int jb = 0; jb < kItems; jb += NC) {
+        const int j = jb + tid;
+        int2 q[3];
+        bool e[3] = {false, false, false};
+        if (j < kItems) {
+            const int item = kEmitItems<TX, TY, TZ>.v[j];
+            const int c = item >> 2, f = item & 3;
+            const int ix = c % TX, iy = (c / TX) % TY, iz = c / (TX * TY);
+            const int cx = ti.bx * TX + ix, cy = ti.by * TY + iy, cz = ti.bz * TZ + iz;
+            if (cx < L && cy < L && cz < L) {
+                const int xm = cx == 0 ? L - 1 : cx - 1, ym = cy == 0 ? L - 1 : cy - 1, zm = cz == 0 ? L - 1 : cz - 1;
+                const uint64_t vb = (f < 2) ? kVert0 : kVert1;
+                bool outside = false;
+                int id[4];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const uint32_t v = (uint32_t)(vb >> (8 * (4 * (f & 1) + mu))) & 0xFFu;
-            const int code = (int)(v >> 4), site = (int)(v & 15u);
-            const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
-            const int nx = (mk & 1u) ? xm : cx, ny = (mk & 2u) ? ym : cy, nz = (mk & 4u) ? zm : cz;
-            const NbrCell nb = ti.at(nx, ny, nz);
-            if (nb.lcell >= 0) {
-                id[mu] = (int)node(P, node_off(16 * nb.lcell + site)) | kTag;
-            } else {
-                id[mu] = 16 * nb.gcell + site;
-                outside = true;
+                for (int mu = 0; mu < 4; ++mu) {
+                    const uint32_t v = (uint32_t)(vb >> (8 * (4 * (f & 1) + mu))) & 0xFFu;
+                    const int code = (int)(v >> 4), site = (int)(v & 15u);
+                    const uint32_t mk = (kLowerAxes >> (3 * code)) & 7u;
+                    const int nx = (mk & 1u) ? xm : cx, ny = (mk & 2u) ? ym : cy, nz = (mk & 4u) ? zm : cz;
+                    const NbrCell nb = ti.at(nx, ny, nz);
+                    if (nb.lcell >= 0) {
+                        id[mu] = (int)node(P, node_off(16 * nb.lcell + site)) | kTag;
+                    } else {
+                        id[mu] = 16 * nb.gcell + site;
+                        outside = true;
+                    }
+                }
+                if (outside) {
+                    const uint32_t code = K4[(DA[c] >> (6 * f)) & 63u];
+#pragma unroll
+                    for (int mu = 1; mu < 4; ++mu) {
+                        const int rp = (code >> (2 * mu)) & 3;
+                        const int rid = rp == 0 ? id[0] : (rp == 1 ? id[1] : id[2]);
+                        e[mu - 1] = rp != mu && rid != id[mu];
+                        q[mu - 1] = make_int2(rid, id[mu]);
+                    }
+                }
             }
         }
-        if (!outside) continue;
-        const uint32_t code = K4[(DA[c] >> (6 * f)) & 63u];
-        int2 pr[3];
-        unsigned npair = 0;
-#pragma unroll
-        for (int mu = 1; mu < 4; ++mu) {
-            const int rp = (code >> (2 * mu)) & 3;
-            const int rid = rp == 0 ? id[0] : (rp == 1 ? id[1] : id[2]);
-            const bool emit = rp != mu && rid != id[mu];
-            pr[mu - 1] = emit ? make_int2(rid, id[mu]) : make_int2(-1, -1);
-            npair += emit;
+        const uint32_t npair = (uint32_t)e[0] + (uint32_t)e[1] + (uint32_t)e[2];
+        const uint64_t b0 = __ballot(npair & 1u), b1 = __ballot(npair & 2u);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u)) +
+                               2u * __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
+        const int wave = tid >> 6;
+        if ((tid & 63) == 0) U[wave] = (uint32_t)(__popcll(b0) + 2 * __popcll(b1));
+        __syncthreads();
+        int at = placed + (int)below, total = 0;
+        for (int w = 0; w < NC / 64; ++w) {
+            const int t = (int)U[w];
+            at += w < wave ? t : 0;
+            total += t;
         }
-        if (npair) {
-            unsigned at = atomicAdd(cursor, npair);
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                if (pr[k].x != -1) list[at++] = pr[k];
+        for (int k = 0; k < 3; ++k) {
+            if (e[k]) list[at] = q[k];
+            at += e[k];
         }
+        placed += total;
+        __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) d.pairs[(int64_t)tile * d.list_stride] = (int)*cursor;
+    if (tid == 0) d.pairs[(int64_t)tile * d.list_stride] = placed;
 }
 
 // ------------------------------------------------------- forest passes ---
