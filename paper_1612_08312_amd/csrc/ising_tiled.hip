@@ -42,7 +42,6 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     __shared__ uint32_t U[kUnionsPerCell * NC];
     __shared__ uint8_t K4[64];
     __shared__ int64_t red[16];
-    __shared__ unsigned cursor;
 
     const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
@@ -90,7 +89,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
         aligned_count = (int)__popcll(al);
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4);
     const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - 48) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }

@@ -75,7 +75,6 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     __shared__ uint32_t DA[NC];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
-    __shared__ unsigned cursor;
 
     const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
@@ -177,7 +176,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
             }
         }
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, DA, K4, &cursor);
+    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, DA, K4);
     const double b = block_sum<double>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }

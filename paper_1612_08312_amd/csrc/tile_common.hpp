@@ -397,7 +397,7 @@ template <int TX, int TY, int TZ>
 __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
                                                 int lcid, bool valid, int cell, uint64_t act,
                                                 const int (&lc)[kNCellCodes], uint32_t *P, uint32_t *U, uint32_t *DA,
-                                                const uint8_t *K4, unsigned *cursor)
+                                                const uint8_t *K4)
 {
     constexpr int NC = TX * TY * TZ;
     static_assert(NC % 64 == 0, "tiles are whole waves");
@@ -416,11 +416,12 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) node(P, base + 4 * mu) = base + 4 * ((code >> (2 * mu)) & 3);
     }
-    if (tid == 0) *cursor = 0;
     __syncthreads();
     // Down tetrahedra, inside the tile: spanning edges, packed as two 16-bit
     // forest slots (17 NC < 2^16).
     uint32_t un[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) un[k] = 0xFFFFFFFFu;  // no union (also for threads without a cell)
     unsigned nun = 0;
     if (valid) {
 #pragma unroll
@@ -445,8 +446,26 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
             }
         }
     }
+    // The thread's unions go after those of the lanes below it (four ballots
+    // of its 0..12 count) and of the lower waves (totals in DA, free here).
+    uint32_t below = 0, wtot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        const uint64_t b = __ballot((nun >> bit) & 1u);
+        below += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u)) << bit;
+        wtot += (uint32_t)__popcll(b) << bit;
+    }
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) DA[wave] = wtot;
+    __syncthreads();
+    int ntotal = 0;
+    unsigned at = below;
+    for (int w = 0; w < NC / 64; ++w) {
+        const int t = (int)DA[w];
+        at += w < wave ? t : 0;
+        ntotal += t;
+    }
     if (nun) {
-        unsigned at = atomicAdd(cursor, nun);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             if (un[k] == 0xFFFFFFFFu) continue;
@@ -459,7 +478,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     // Each thread takes a contiguous run of the list: a cell's unions sit
     // together in it, so the lanes of a wave work on different cells' roots.
     {
-        const int nlist = min((int)*cursor, kCap);
+        const int nlist = min(ntotal, kCap);
         const int per = (nlist + NC - 1) / NC;
         const int kb = min(tid * per, nlist), ke = min(kb + per, nlist);
         for (int k = kb; k < ke; ++k) lds_unite(P, (U[k] >> 14) & ~3u, (U[k] & 0xFFFFu) << 2);
