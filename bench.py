@@ -53,7 +53,7 @@ def bytes_per_site(shape):
 # each scaled by the same counter's reading for the probe's 256 MiB copy.
 # Valid only for the kernel sources they were taken with (fingerprint).
 MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
-    "local": ("b86238b36a9ad38f", 216922650),  # profiles/k_local_ising_L128_traffic.md
+    "local": ("630790f62e1ca744", 217102692),  # profiles/k_local_ising_L128_traffic.md
 }
 
 
