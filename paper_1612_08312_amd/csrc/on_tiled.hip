@@ -13,10 +13,11 @@
 //   bond active iff (double)x > -log1p(-u), u = (r32 + 0.5) 2^-32, r32 =
 //   word (b mod 4) of Philox(b/4, t, BOND)
 //   reflection s_k <- fmaf(-2 sigma, r_k, s_k)
-// The log1p is evaluated only when x lies between the two bounds
-// u <= -log1p(-u) <= u / (1 - u); outside that window both bounds give the
-// same answer as the exact comparison.  Energies and magnetisations are
-// FP64 sums of the FP32 spins.
+// The FP64 log1p is evaluated only when x lies within 1e-4 (1 + t) of
+// t = -ln(1 - u) computed in FP32 with the native base-2 logarithm: that
+// margin exceeds the FP32 error by orders of magnitude, so outside it the FP32
+// comparison gives the same answer as the exact one.  Energies and
+// magnetisations are FP64 sums of the FP32 spins.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -55,15 +56,22 @@ __device__ __forceinline__ float project(const float v[NV], const float r[NV])
     return sig;
 }
 
-// Exact activation decision of one bond (see the file comment).
+// The exact comparison, out of line: it is rarely reached, and 48 inlined
+// copies per cell would swell the tile kernel's code.
+__device__ __noinline__ bool on_bond_exact(float x, double u) { return (double)x > -log1p(-u); }
+
+// Exact activation decision of one bond (see the file comment).  1 - u is
+// exact in FP64 and at least 2^-33, so its FP32 rounding is a normal number
+// within a relative 2^-24.
 __device__ __forceinline__ bool on_bond_active(float x, uint32_t r32)
 {
     if (!(x > 0.0f)) return false;
-    const double xd = (double)x;
     const double u = ((double)r32 + 0.5) * 0x1p-32;
-    if (xd <= u) return false;
-    if (xd > u / (1.0 - u) * (1.0 + 1e-13)) return true;
-    return xd > -log1p(-u);
+    const float t = -0.6931472f * __log2f((float)(1.0 - u));  // native base-2 logarithm
+    const float m = 1e-4f * (1.0f + t);
+    if (x > t + m) return true;
+    if (x < t - m) return false;
+    return on_bond_exact(x, u);
 }
 
 template <int NV, int TX, int TY, int TZ>
@@ -100,17 +108,18 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     uint64_t act = 0;
     double esum = 0.0;
     int lc[kNCellCodes];
+    NbrCell nb[kNCellCodes];
+    float own[NV][16];
 #pragma unroll
     for (int q = 0; q < kNCellCodes; ++q) lc[q] = -1;
-    if (valid) {
-        NbrCell nb[kNCellCodes];
-        float r[NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) own[k][q] = 0.0f;
+    if (valid) {
         ti.neighbours(x, y, z, cell, lcid, nb);
 #pragma unroll
         for (int q = 0; q < kNCellCodes; ++q) lc[q] = nb[q].lcell;
-        float own[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const float4 *S4 = reinterpret_cast<const float4 *>(s + (int64_t)k * N) + 4 * (int64_t)cell;
@@ -123,17 +132,41 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
                 own[k][4 * q + 3] = v.w;
             }
         }
-        float dv[NV][16];
+    }
+    // Down-tetrahedron vertices: those in the tile are read from the tile's
+    // spins, staged one component at a time in the forest array (free until
+    // the tile components start; site q of local cell c at q NC + c), those
+    // outside the tile from global memory.
+    float dv[NV][16];
+    float *SP = reinterpret_cast<float *>(P);
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
+    for (int k = 0; k < NV; ++k) {
 #pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-                const SiteRef R = down_vertex(f, mu);
+        for (int q = 0; q < 16; ++q) SP[q * NC + lcid] = own[k][q];
+        __syncthreads();
+        if (valid) {
 #pragma unroll
-                for (int k = 0; k < NV; ++k)
-                    dv[k][4 * f + mu] = R.cell == kSelf ? own[k][R.site]
-                                                        : s[(int64_t)k * N + 16 * nb[R.cell].gcell + R.site];
-            }
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu) {
+                    const SiteRef R = down_vertex(f, mu);
+                    float v;
+                    if (R.cell == kSelf) {
+                        v = own[k][R.site];
+                    } else {
+                        const int l = lc[R.cell];
+                        if (l >= 0) v = SP[R.site * NC + l];
+                        else v = s[(int64_t)k * N + 16 * nb[R.cell].gcell + R.site];
+                    }
+                    dv[k][4 * f + mu] = v;
+                }
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        float r[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
         float sig_own[16], sig_dv[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
