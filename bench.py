@@ -113,7 +113,39 @@ def cpu_baseline(L, T, seed, sweeps):
     dt = time.perf_counter() - t0
     return dict(value=o.N * sweeps / dt, unit="spin-updates/s", cores=1, kind="oracle",
                 sample=f"{sweeps} sweeps of one Ising L={L} lattice at T={T} (N={o.N}), "
-                       f"random start, single-threaded C oracle, lattice build not timed")
+                       f"random start, single-threaded C oracle, lattice build not timed",
+                host=cpu_model(), host_threads=os.cpu_count())
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_peak_gbs(dev, mib=1024, reps=5):
+    """Achievable HBM bandwidth: best of `reps` device-to-device copies of
+    `mib` MiB (bytes read plus bytes written over the copy's duration)."""
+    import torch
+
+    a = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2 * (mib << 20) / (best * 1e-3) / 1e9
 
 
 def batched_vs_plain(sweeps, stream, dev):
@@ -361,6 +393,13 @@ def main():
     for lt in lats:
         lt.close()
 
+    # Outside the timed region: the achievable copy bandwidth and the Philox
+    # throughput (the ALU side of the tile pass: 3 blocks per cell and sweep,
+    # plus a rare fourth for near-threshold bonds).
+    copy_gbs = copy_peak_gbs(dev)
+    philox_rate, philox_fold = pyrosw.pyro_sw_philox_rate(1 << 28, 3, 1)
+    philox_blocks = 3 * (N // 16)
+
     updates = N * len(lats) * args.steps
     value = updates / dt
     dom_avg_s = dom_ms / max(dom_n, 1) / 1e3
@@ -415,6 +454,15 @@ def main():
             "mean_launch_us": dom_avg_s * 1e6,
             "timed_launches": dom_n,
             "launches_per_step": launches_per_step,
+            "copy_GBps": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
+        },
+        "philox": {
+            "blocks_per_s": philox_rate,
+            "blocks_per_lattice_sweep": philox_blocks,
+            "us_per_lattice_sweep": philox_blocks / philox_rate * 1e6,
+            "share_of_step": philox_blocks * len(lats) / philox_rate / (dt / args.steps),
+            "fold": philox_fold,
         },
         "sweep_alg_roofline_frac": value * SWEEP_BYTES_PER_SITE / (HBM_PEAK_GBS * 1e9),
         "binder_U_second_half": binder,

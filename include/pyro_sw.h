@@ -301,6 +301,21 @@ int pyro_sw_server_take(pyro_sw_server *s, int64_t id, pyro_sw_record *out, int6
 int pyro_sw_server_clock(pyro_sw_server *s, double *seconds);
 int pyro_sw_server_destroy(pyro_sw_server *s);
 
+/*
+ * Measurement helper, not part of a sweep: throughput on the current device
+ * of the Philox4x32-10 generator that every random draw of a sweep uses
+ * (counter, key and rounds as in pyro_sw_init).  Draws `calls` blocks with
+ * counters (i, 0x5EED, BOND stream, 0) for i = 0 .. calls-1 and key = seed,
+ * spread over the whole GPU, and XOR-folds all their output words so that no
+ * block is skipped; the launch is timed `repeats` times with HIP events.
+ *   calls_per_second  blocks per second of the fastest launch (out)
+ *   fold              XOR of every output word of every block (out), for a
+ *                     check against a host implementation
+ * Synchronous; allocates and frees a 4-byte device buffer and a stream.
+ * EINVAL for calls outside [1, 2^32], repeats < 1 or NULL outputs.
+ */
+int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls_per_second, uint32_t *fold);
+
 /* Synchronise and free everything the library allocated.  NULL is a no-op. */
 int pyro_sw_destroy(pyro_sw *h);
 

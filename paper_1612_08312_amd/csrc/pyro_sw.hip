@@ -42,6 +42,24 @@ namespace {
 
 int fail(int status, const std::string &msg) { return record_error(status, msg.c_str()); }
 
+// Philox throughput probe: each thread draws the blocks i = gid, gid +
+// stride, ... below `calls` and XOR-folds their words; each block writes its
+// fold to out[blockIdx.x] (the host folds those).
+__global__ __launch_bounds__(256) void k_philox_rate(uint64_t calls, PhiloxKey key, uint32_t *out)
+{
+    __shared__ uint32_t wf[4];
+    uint32_t acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < calls; i += stride) {
+        const uint4 r = philox4x32_10((uint32_t)i, 0x5EEDu, kStreamBond, 0u, key);
+        acc ^= r.x ^ r.y ^ r.z ^ r.w;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) wf[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = wf[0] ^ wf[1] ^ wf[2] ^ wf[3];
+}
+
 constexpr int kRing = 16384;  // device records per lattice before a forced drain
 constexpr int kMaxSlices = 8;  // concurrent slices of a group
 constexpr size_t kAlign = 256;
@@ -832,6 +850,46 @@ int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, doub
     int rc = usable(h);
     if (rc) return rc;
     return report_times(h->timer, &h->broken, names, launches, ms, cap, n_out);
+}
+
+int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls_per_second, uint32_t *fold)
+{
+    if (calls < 1 || calls > ((int64_t)1 << 32)) return fail(PYRO_EINVAL, "calls must be in [1, 2^32]");
+    if (repeats < 1) return fail(PYRO_EINVAL, "repeats must be >= 1");
+    if (!calls_per_second || !fold) return fail(PYRO_EINVAL, "outputs must not be NULL");
+    constexpr int kBlocks = 2048;  // 8 workgroups of 256 threads per CU
+    uint32_t *d_out = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<uint32_t> folds(kBlocks);
+    float best = -1.0f;
+    hipError_t e = hipMalloc(&d_out, sizeof(uint32_t) * kBlocks);
+    if (e == hipSuccess) e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int r = 0; r < repeats && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) {
+            k_philox_rate<<<kBlocks, 256, 0, st>>>((uint64_t)calls, philox_key(seed), d_out);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best < 0.0f || ms < best)) best = ms;
+    }
+    if (e == hipSuccess) e = hipMemcpy(folds.data(), d_out, sizeof(uint32_t) * kBlocks, hipMemcpyDeviceToHost);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (st) (void)hipStreamDestroy(st);
+    if (d_out) (void)hipFree(d_out);
+    if (e != hipSuccess) return fail(PYRO_EDEVICE, std::string("philox rate: ") + hipGetErrorString(e));
+    uint32_t f = 0;
+    for (uint32_t v : folds) f ^= v;
+    *fold = f;
+    *calls_per_second = (double)calls / (std::max(best, 1e-6f) * 1e-3);
+    return PYRO_OK;
 }
 
 int pyro_sw_destroy(pyro_sw *h)

@@ -47,6 +47,7 @@ EXPORTS = (
     "pyro_sw_group_destroy", "pyro_sw_group_set_slices",
     "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
     "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
+    "pyro_sw_philox_rate",
 )
 
 PYRO_JOB_QUEUED, PYRO_JOB_RUNNING, PYRO_JOB_DONE = 0, 1, 2
@@ -105,6 +106,7 @@ def load_library():
     lib.pyro_sw_set_timing.argtypes = [vp, i32]
     lib.pyro_sw_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_destroy.argtypes = [vp]
+    lib.pyro_sw_philox_rate.argtypes = [i64, i32, u64, P(f64), P(ctypes.c_uint32)]
     lib.pyro_sw_set_tile_shape.argtypes = [vp, i32]
     lib.pyro_sw_group_create.argtypes = [P(vp), P(vp), i32, vp]
     lib.pyro_sw_group_sweep.argtypes = [vp, i64, P(i64)]
@@ -292,6 +294,15 @@ def pyro_sw_group_destroy(g):
     if g is not None and g.value:
         _check(load_library().pyro_sw_group_destroy(g), "pyro_sw_group_destroy")
         g.value = None
+
+
+def pyro_sw_philox_rate(calls: int, repeats: int = 3, seed: int = 1):
+    """Philox4x32-10 blocks per second on the current device, and the XOR fold
+    of all output words of blocks (i, 0x5EED, BOND, 0), i < calls, key seed."""
+    rate, fold = ctypes.c_double(), ctypes.c_uint32()
+    _check(load_library().pyro_sw_philox_rate(int(calls), int(repeats), int(seed), ctypes.byref(rate),
+                                              ctypes.byref(fold)), "pyro_sw_philox_rate")
+    return rate.value, fold.value
 
 
 def pyro_sw_destroy(h):

@@ -93,3 +93,15 @@ def test_server_null_calls():
 def test_group_set_slices_null():
     lib = pyrosw.load_library()
     assert lib.pyro_sw_group_set_slices(None, 2) == pyrosw.PYRO_EINVAL
+
+
+@pytest.mark.parametrize("calls,repeats", [(0, 1), (-5, 1), ((1 << 32) + 1, 1), (16, 0)])
+def test_philox_rate_rejects_bad_arguments_without_a_device(calls, repeats):
+    with pytest.raises(pyrosw.PyroSWError) as ei:
+        pyrosw.pyro_sw_philox_rate(calls, repeats)
+    assert ei.value.status == pyrosw.PYRO_EINVAL
+
+
+def test_philox_rate_null_outputs():
+    lib = pyrosw.load_library()
+    assert lib.pyro_sw_philox_rate(16, 1, 1, None, None) == pyrosw.PYRO_EINVAL
