@@ -75,14 +75,20 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     if (valid) {
         NbrCell nb[kNCellCodes];
         ti.neighbours(x, y, z, cell, lcid, nb);
+        // Spins of the neighbour cells outside the tile: every lane issues all
+        // six loads (its own cell, a cache hit, where the neighbour is in the
+        // tile), so they are in flight together instead of one divergent
+        // branch at a time.
+        int4 gv[kNCellCodes];
+#pragma unroll
+        for (int q = 1; q < kNCellCodes; ++q)
+            gv[q] = reinterpret_cast<const int4 *>(s)[nb[q].lcell >= 0 ? cell : nb[q].gcell];
         uint32_t nm[kNCellCodes];
         nm[kSelf] = m;
 #pragma unroll
         for (int q = 0; q < kNCellCodes; ++q) {
             lc[q] = nb[q].lcell;
-            if (q > 0)
-                nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell]
-                                         : spin_mask16(reinterpret_cast<const int4 *>(s)[nb[q].gcell]);
+            if (q > 0) nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell] : spin_mask16(gv[q]);
         }
         const uint32_t dm = down_mask16(m, nm[kMx], nm[kMy], nm[kMz], nm[kMyMz], nm[kMxMz], nm[kMxMy]);
         const uint64_t al = aligned48(m, dm);
