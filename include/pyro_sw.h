@@ -152,7 +152,9 @@ int pyro_sw_set_temperature(pyro_sw *h, double T);
  * Tile shape of the cluster labeling: the lattice is cut into boxes of cells,
  * each labelled in one workgroup's local memory before the boxes are merged.
  * The shape changes speed only, never results (labels are canonical and all
- * draws are keyed by sweep and site or bond).  A new handle uses 8x8x8.
+ * draws are keyed by sweep and site or bond).  A new handle uses 8x8x8
+ * for L >= 96, 8x8x4 for 48 <= L < 96 and 8x4x4 below (a group without an
+ * autotuned shape applies the same rule to its largest L).
  */
 enum { PYRO_TILE_8x8x4 = 0, PYRO_TILE_8x4x4 = 1, PYRO_TILE_4x4x4 = 2, PYRO_TILE_8x8x8 = 3, PYRO_TILE_16x8x8 = 4 };
 int pyro_sw_set_tile_shape(pyro_sw *h, int shape);

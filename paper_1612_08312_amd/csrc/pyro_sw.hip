@@ -60,6 +60,10 @@ __global__ __launch_bounds__(256) void k_philox_rate(uint64_t calls, PhiloxKey k
     if (threadIdx.x == 0) out[blockIdx.x] = wf[0] ^ wf[1] ^ wf[2] ^ wf[3];
 }
 
+// Default tile shape for lattices of edge up to L (measured on MI355X):
+// small lattices need smaller tiles to give every CU work.
+int default_tile_shape(int L) { return L >= 96 ? kTile888 : (L >= 48 ? kTile884 : kTile844); }
+
 constexpr int kRing = 16384;  // device records per lattice before a forced drain
 constexpr int kMaxSlices = 8;  // concurrent slices of a group
 constexpr size_t kAlign = 256;
@@ -245,7 +249,7 @@ struct pyro_sw {
     int busy = 0;  // nonzero while a group sweeps this lattice
     // solo sweeps
     ChainTables solo;
-    int solo_shape = kTile888;
+    int solo_shape = kTile888;  // set from L at init (default_tile_shape)
     hipGraphExec_t solo_exec = nullptr;
     uint64_t param_version = 1, solo_version = 0;
     Timer timer;
@@ -546,6 +550,7 @@ int create(pyro_sw **out, int L, int model, double T, double J, uint64_t seed, i
     pyro_sw *h = new (std::nothrow) pyro_sw();
     if (!h) return fail(PYRO_ENOMEM, "host allocation failed");
     h->L = L;
+    h->solo_shape = default_tile_shape(L);
     h->model = model;
     h->ncell = (int64_t)L * L * L;
     h->N = 16 * h->ncell;
@@ -950,7 +955,9 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
         if (ct.reps.empty()) continue;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(ct));
-        ct.shape = it != g_tune_cache.end() ? it->second : kTile888;
+        int lmax = 1;
+        for (const pyro_sw *h : ct.reps) lmax = std::max(lmax, h->L);
+        ct.shape = it != g_tune_cache.end() ? it->second : default_tile_shape(lmax);
     }
     if (int rc = make_slices(g, std::min(n, kMaxSlices))) {
         pyro_sw_group_destroy(g);
