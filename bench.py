@@ -53,7 +53,7 @@ def bytes_per_site(shape):
 # each scaled by the same counter's reading for the probe's 256 MiB copy.
 # Valid only for the kernel sources they were taken with (fingerprint).
 MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
-    "local": ("908379f348583a33", 216857381),  # profiles/k_local_ising_L128_traffic.md
+    "local": ("eefa62d5b9bb4604", 216854675),  # profiles/k_local_ising_L128_traffic.md
 }
 
 
