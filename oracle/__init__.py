@@ -28,6 +28,7 @@ PLANT_FLIP_ALL = 2
 PLANT_DROP_BONDS = 3
 PLANT_REFLECT_SIGN = 4
 PLANT_ANTI = 5
+PLANT_VACANT_JOIN = 6
 
 # Per-sweep record, same field order as the C struct ``orc_record``.
 RECORD_DTYPE = np.dtype(

@@ -24,6 +24,11 @@
  *     probability 1/2.
  *   - Measurement: M, m = M/N, m^2, m^4 per sweep (Sec. 3.1, Eq. 2) and the
  *     energy E = H (Eq. 1).
+ *   - Site dilution (the extension named in Sec. 4): a vacant site is a
+ *     zero spin (Ising 0, O(n) the zero vector).  It carries no bond (for
+ *     O(n) the projected product is 0, so the bond never activates), stays
+ *     its own one-site cluster and stays zero under flips; m is M/N with N
+ *     all sites, vacant or not.
  *   - Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
  *     counter = (unit, sweep, stream, attempt), key = seed.  The paper does
  *     not name its generator; the counter layout is this project's reading.
@@ -57,6 +62,7 @@
 #define PLANT_DROP_BONDS 3  /* bonds with odd index never activate */
 #define PLANT_REFLECT_SIGN 4 /* O(n): s + 2 (s.r) r instead of s - 2 (s.r) r */
 #define PLANT_ANTI 5        /* Ising: activate antiparallel instead of parallel */
+#define PLANT_VACANT_JOIN 6 /* Ising: let two vacant sites activate their bond */
 
 typedef struct {
     int64_t sweep;    /* global 0-based index of the sweep this record follows */
@@ -583,7 +589,10 @@ static void sweep_ising(orc *h)
 {
     for (int64_t b = 0; b < h->NB; ++b) {
         int8_t sa = h->s8[h->ba[b]], sb = h->s8[h->bb[b]];
-        int parallel = (h->plant == PLANT_ANTI) ? (sa != sb) : (sa == sb);
+        /* A vacant site (spin 0, site dilution) carries no bond: a bond is a
+         * candidate only when both ends hold equal nonzero spins. */
+        int parallel = (h->plant == PLANT_ANTI) ? (sa != sb)
+                                                 : (sa == sb && (sa != 0 || h->plant == PLANT_VACANT_JOIN));
         uint8_t act = 0;
         if (parallel) act = (uint64_t)ising_bond_uniform(h->seed, (uint64_t)b, h->t) < h->thr;
         if (h->plant == PLANT_DROP_BONDS && (b & 1)) act = 0;

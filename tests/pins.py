@@ -65,15 +65,16 @@ def binned_binder(m2: np.ndarray, m4: np.ndarray, nbins: int = 50):
 # --------------------------------------------------------------------------
 # Exact enumeration of the Ising model on a small graph.
 # --------------------------------------------------------------------------
-def ising_exact(N: int, a: np.ndarray, b: np.ndarray, T: float, J: float = 1.0):
-    """<E>, <m^2>, <m^4> and U by summing over all 2^N states (Eq. 1, Eq. 2)."""
+def ising_exact(N: int, a: np.ndarray, b: np.ndarray, T: float, J: float = 1.0, norm: int = None):
+    """<E>, <m^2>, <m^4> and U by summing over all 2^N states (Eq. 1, Eq. 2);
+    m = M / norm (default N; a diluted lattice passes its full site count)."""
     states = ((np.arange(2 ** N)[:, None] >> np.arange(N)[None, :]) & 1).astype(np.int64)
     s = 1 - 2 * states
     B = (s[:, a] * s[:, b]).sum(axis=1)
     E = -J * B
     w = np.exp(-(E - E.min()) / T)
     Z = w.sum()
-    m = s.sum(axis=1) / N
+    m = s.sum(axis=1) / (N if norm is None else norm)
     e_mean = float((w * E).sum() / Z)
     m2 = float((w * m ** 2).sum() / Z)
     m4 = float((w * m ** 4).sum() / Z)
