@@ -86,10 +86,17 @@ class Protocol:
         return self.discard + self.measure
 
 
-def default_temperatures(model: int, n: int = 13, rel_halfwidth: float = 6e-4):
+# Half-width of the default window, relative to T_c: the scaling variable
+# t (N^(1/3))^(1/nu) then spans about +-0.6 to +-1 at L = 32 for every model
+# (U of the continuous models varies more slowly with it).
+WINDOW = {workloads.ISING: 6e-4, workloads.XY: 1.2e-3, workloads.HEISENBERG: 2e-3}
+
+
+def default_temperatures(model: int, n: int = 13, rel_halfwidth: float = None):
     """n temperatures spaced evenly over T_c (1 +- rel_halfwidth) around the
     paper's estimate of T_c (the window only sets where to look)."""
     tc = workloads.TC[model]
+    rel_halfwidth = WINDOW[model] if rel_halfwidth is None else rel_halfwidth
     return tuple(float(t) for t in tc * (1.0 + np.linspace(-rel_halfwidth, rel_halfwidth, n)))
 
 
@@ -373,7 +380,7 @@ def main(argv=None):
     ap.add_argument("--model", type=int, default=1, choices=(1, 2, 3))
     ap.add_argument("--L", type=int, nargs="+", default=[32, 48, 64, 96])
     ap.add_argument("--temps", type=float, nargs="*", default=None,
-                    help="temperatures (default: 13 over T_c (1 +- 6e-4))")
+                    help="temperatures (default: 13 over T_c (1 +- w), w from WINDOW)")
     ap.add_argument("--discard", type=int, default=10_000)
     ap.add_argument("--measure", type=int, default=200_000)
     ap.add_argument("--runs", type=int, default=5)

@@ -1,0 +1,62 @@
+"""The finite-size-scaling driver on the GPU (Sec. 2 protocol, Sec. 3.1
+analysis) at small sizes: every lattice of the scan follows its solo
+trajectory bit for bit, the moment ratio behaves as the paper describes
+(between its T -> 0 and T -> infinity limits, ordered by size on either side
+of T_c), and the Binder crossings of L = 8, 12, 16 fall near the paper's T_c.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1612_08312_amd import fss, pyrosw, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def solo_m2(L, model, T, seed, sweeps):
+    lt = pyrosw.Lattice(L=L, model=model, T=T, seed=seed, start=pyrosw.PYRO_START_RANDOM)
+    lt.sweep(sweeps)
+    rec = lt.moments()
+    lt.close()
+    return rec
+
+
+@pytest.mark.parametrize("model", [workloads.ISING, workloads.XY])
+def test_small_scan(model):
+    tc = workloads.TC[model]
+    temps = tuple(float(t) for t in tc * (1.0 + np.linspace(-0.012, 0.012, 9)))
+    p = fss.Protocol(model=model, Ls=(8, 12, 16), temps=temps, discard=300, measure=3000,
+                     runs=3, seed=77, chunk=1100, autotune=(model == workloads.ISING))
+    say("GPU case: FSS scan model %d, L %s, %d temperatures, %d + %d sweeps x %d runs"
+        % (model, p.Ls, len(temps), p.discard, p.measure, p.runs))
+    data = fss.run_protocol(p, log=say)
+
+    # one member against the same lattice swept alone
+    L, ti, r, seed = p.members()[len(temps) * p.runs + 4 * p.runs + 1]
+    rec = solo_m2(L, model, temps[ti], seed, p.sweeps_per_member())
+    np.testing.assert_array_equal(data.m2[L][ti][r], rec["m2"][p.discard:])
+    np.testing.assert_array_equal(data.m4[L][ti][r], rec["m4"][p.discard:])
+    assert len(data.m2[L][ti][r]) == p.measure
+
+    rm = fss.run_means(data)
+    U, dU, m2, dm2 = fss.estimates(rm)
+    hi = (model + 2.0) / model  # the T -> infinity limit of U (Sec. 3.1)
+    assert np.all(U > 1.0) and np.all(U < hi)
+    assert np.all(np.isfinite(dU)) and np.all(dU > 0)
+    # below T_c larger lattices are more ordered (smaller U), above less
+    assert np.all(U[:, 0] < U[:, -1])
+    assert U[0, 0] > U[-1, 0] and U[0, -1] < U[-1, -1]
+    # <m^2> falls with T and, at the top of the window, with L
+    assert np.all(m2[:, 0] > m2[:, -1]) and m2[0, -1] > m2[-1, -1]
+
+    cr = fss.crossings(temps, rm, p.Ls)
+    say("crossings", cr)
+    for (_, _, t, e) in cr:
+        # small lattices: corrections to scaling move the crossing by up to
+        # about half a percent of T_c
+        assert abs(t - tc) < 0.006 * tc, (t, e)
