@@ -309,6 +309,36 @@ def on_throughput(sweeps, stream, dev):
     return out
 
 
+def diluted_throughput(sweeps, stream, dev):
+    """Site-diluted Ising lattice (L = 128, 10% vacant sites, T = 3.8) against
+    the pure lattice at the same temperature: spin-updates/s of each (all N
+    sites counted), one lattice at a time, after 20 warm-up sweeps."""
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    c = workloads.DILUTED_ISING_L128
+    N = workloads.n_sites(c["L"])
+    out = {}
+    for name, vac in (("diluted", c["vacancy"]), ("pure", 0.0)):
+        lt = pyrosw.Lattice(L=c["L"], model=c["model"], T=c["T"], J=c["J"], seed=c["seed"],
+                            start=pyrosw.PYRO_START_COLD, device=dev, stream=stream)
+        lt.set_spins(workloads.diluted_spins(N, c["model"], vac, c["seed"]), 0)
+        lt.sweep(20)
+        lt.moments()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lt.sweep(sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = lt.moments()
+        lt.close()
+        out[name] = {"vacancy": vac, "spin_updates_per_s": N * sweeps / dt, "us_per_sweep": dt / sweeps * 1e6,
+                     "mean_m2": float(rec["m2"].mean())}
+    out.update(workload="ising_pyrochlore_L128_site_diluted", L=c["L"], T=c["T"], sweeps=sweeps)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +354,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the job server")
     ap.add_argument("--serve-quantum-ms", type=float, default=20.0, help="lane quantum of the job server")
     ap.add_argument("--on-sweeps", type=int, default=500, help="sweeps of the XY and Heisenberg L=64 leg (0: skip)")
+    ap.add_argument("--diluted-sweeps", type=int, default=500,
+                    help="sweeps of the site-diluted Ising L=128 leg and its pure twin (0: skip)")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter-collection workload and exit")
     ap.add_argument("--roofline-steps", type=int, default=200,
                     help="steps of the pass that times the dominant kernel with HIP events")
@@ -471,6 +503,9 @@ def main():
     if args.on_sweeps > 0:
         log(f"bench: XY and Heisenberg L=64, {args.on_sweeps} sweeps each")
         out["on"] = on_throughput(args.on_sweeps, stream, dev)
+    if args.diluted_sweeps > 0:
+        log(f"bench: site-diluted and pure Ising L=128, {args.diluted_sweeps} sweeps each")
+        out["diluted"] = diluted_throughput(args.diluted_sweeps, stream, dev)
     if args.batch_sweeps > 0:
         log(f"bench: 96-replica batch, {args.batch_sweeps} sweeps, batched then plain")
         out["batched"] = batched_vs_plain(args.batch_sweeps, stream, dev)

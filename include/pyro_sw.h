@@ -131,6 +131,14 @@ int pyro_sw_moments(pyro_sw *h, pyro_sw_record *out, int64_t cap, int64_t *n_out
  * [N] (+1 / -1); O(n) float [n][N], component-major.  bytes must equal that
  * size.  set_spins also sets the global index of the next sweep (random
  * draws depend on it), and discards queued records.  Synchronising.
+ *
+ * Site dilution (the random-system extension of Sec. 4): a zero spin (Ising
+ * 0, O(n) the zero vector) is a vacant site.  It carries no bond, stays its
+ * own one-site cluster and stays zero; E sums over bonds with two occupied
+ * ends and m = M/N counts all N sites.  For Ising, set_spins with a vacant
+ * site allocates one library-owned device array of 8 bytes per cell (the
+ * bonds with two occupied ends), kept until pyro_sw_destroy.  Errors:
+ * PYRO_EINVAL for an Ising value other than +1, -1, 0; PYRO_ENOMEM.
  */
 int pyro_sw_get_spins(pyro_sw *h, void *host, size_t bytes);
 int pyro_sw_set_spins(pyro_sw *h, const void *host, size_t bytes, int64_t next_sweep);

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     __syncthreads();
 
     uint64_t act = 0;
-    int aligned_count = 0;
+    int aligned_count = 0, nbonds = 48;
     int lc[kNCellCodes];
 #pragma unroll
     for (int q = 0; q < kNCellCodes; ++q) lc[q] = -1;
@@ -91,12 +91,17 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
             if (q > 0) nm[q] = nb[q].lcell >= 0 ? SM[nb[q].lcell] : spin_mask16(gv[q]);
         }
         const uint32_t dm = down_mask16(m, nm[kMx], nm[kMy], nm[kMz], nm[kMyMz], nm[kMxMz], nm[kMxMy]);
-        const uint64_t al = aligned48(m, dm);
+        uint64_t al = aligned48(m, dm);
+        if (d.present) {  // a bond with a vacant end is neither a candidate nor counted in E
+            const uint64_t pm = d.present[cell];
+            al &= pm;
+            nbonds = (int)__popcll(pm);
+        }
         aligned_count = (int)__popcll(al);
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
     tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4);
-    const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - 48) : 0, red);
+    const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - nbonds) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }
 
@@ -162,18 +167,21 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
         int4 *S4 = reinterpret_cast<int4 *>(d.spins);
         const int4 sv = S4[cell];
         uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
-        int down = 0;
+        int down = 0, occupied = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t f4 = (flipmask >> (4 * q)) & 15u;
-            // +1 (0x01) <-> -1 (0xFF) is XOR 0xFE on the flipped bytes
-            const uint32_t fx = ((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
-                                ((f4 >> 3 & 1u) * 0xFE000000u);
+            // +1 (0x01) <-> -1 (0xFF) is XOR 0xFE on the flipped bytes; a
+            // vacant site (0x00) is left alone
+            const uint32_t nz = (((w[q] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w[q]) & 0x80808080u;
+            const uint32_t fx = (((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
+                                 ((f4 >> 3 & 1u) * 0xFE000000u)) & ((nz >> 7) * 0xFEu);
             w[q] ^= fx;
             down += (int)__popc(w[q] & 0x80808080u);
+            occupied += (int)__popc(nz);
         }
         S4[cell] = make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
-        mag = 16 - 2 * down;
+        mag = occupied - 2 * down;
     }
     const int64_t msum = block_sum<int64_t>((int64_t)mag, red);
     if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
@@ -244,7 +252,14 @@ __global__ __launch_bounds__(kBlock) void k_energy_ising(Chain c)
         const uint32_t dm = down_mask16(m, spin_mask16(S4[nb.c[kMx]]), spin_mask16(S4[nb.c[kMy]]),
                                         spin_mask16(S4[nb.c[kMz]]), spin_mask16(S4[nb.c[kMyMz]]),
                                         spin_mask16(S4[nb.c[kMxMz]]), spin_mask16(S4[nb.c[kMxMy]]));
-        B = 2 * (int64_t)__popcll(aligned48(m, dm)) - 48;
+        uint64_t al = aligned48(m, dm);
+        int nbonds = 48;
+        if (d.present) {
+            const uint64_t pm = d.present[cell];
+            al &= pm;
+            nbonds = (int)__popcll(pm);
+        }
+        B = 2 * (int64_t)__popcll(al) - nbonds;
     }
     const int64_t bsum = block_sum<int64_t>(B, red);
     if (threadIdx.x == 0) d.ipart[d.tail_off + blk] = bsum;

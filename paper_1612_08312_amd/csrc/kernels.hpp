@@ -57,6 +57,8 @@ struct RepDesc {
     int *pairs;        // per-tile crossing lists: pair count, root count (set by the unite pass), then
                        // (name, name) pairs, replaced by the distinct local roots when the root count is > 0
     int list_stride;   // ints per tile list (tile shape dependent)
+    const uint64_t *present;  // Ising site dilution: [ncell] masks of the cell's 48 bonds whose two sites
+                              // are occupied (bit j = bond 48 cell + j), or null when no site is vacant
     // constants of the run
     uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
     float x0;                 // O(n): (float)(2J/T)

@@ -22,6 +22,7 @@
 
 #include "../../include/pyro_sw.h"
 #include "kernels.hpp"
+#include "lattice.hpp"
 
 using namespace pyro;
 
@@ -253,6 +254,10 @@ struct pyro_sw {
     hipGraphExec_t solo_exec = nullptr;
     uint64_t param_version = 1, solo_version = 0;
     Timer timer;
+    // Ising site dilution: per-cell masks of the bonds with two occupied ends
+    // (library-owned, allocated on the first set_spins with a vacant site)
+    uint64_t *d_present = nullptr;
+    bool diluted = false;
 };
 
 // A slice of a group's members with its own chains, captured sweep and
@@ -306,6 +311,33 @@ void set_params(pyro_sw *h, double T)
     h->param_version++;
 }
 
+// Bond masks of a site-diluted Ising lattice: bit j of cell c is set when
+// both ends of bond 48 c + j hold a nonzero spin (a vacant site, spin 0,
+// carries no bond).
+void present_masks(const int8_t *s, int L, std::vector<uint64_t> &pm)
+{
+    const int64_t nc = (int64_t)L * L * L;
+    pm.assign((size_t)nc, 0);
+    for (int64_t c = 0; c < nc; ++c) {
+        const int x = (int)(c % L), y = (int)((c / L) % L), z = (int)(c / ((int64_t)L * L));
+        const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
+        int64_t nb[kNCellCodes];
+        nb[kSelf] = c;
+        nb[kMx] = ((int64_t)z * L + y) * L + xm;
+        nb[kMy] = ((int64_t)z * L + ym) * L + x;
+        nb[kMz] = ((int64_t)zm * L + y) * L + x;
+        nb[kMyMz] = ((int64_t)zm * L + ym) * L + x;
+        nb[kMxMz] = ((int64_t)zm * L + y) * L + xm;
+        nb[kMxMy] = ((int64_t)z * L + ym) * L + xm;
+        uint64_t m = 0;
+        for (int j = 0; j < 48; ++j) {
+            const SiteRef a = bond_end_a(j), b = bond_end_b(j);
+            if (s[16 * nb[a.cell] + a.site] != 0 && s[16 * nb[b.cell] + b.site] != 0) m |= 1ull << j;
+        }
+        pm[(size_t)c] = m;
+    }
+}
+
 // Descriptor of a replica for a chain with tile shape `shape`.
 RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int coin_base)
 {
@@ -326,6 +358,7 @@ RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int
     d.ring = (DevRecord *)(h->work + h->ly.ring);
     d.pairs = (int *)(h->work + h->ly.pairs);
     d.list_stride = tile_list_stride(shape);
+    d.present = h->diluted ? h->d_present : nullptr;
     d.thr_hi = h->thr_hi;
     d.thr_lo = h->thr_lo;
     d.x0 = h->x0;
@@ -766,12 +799,27 @@ int pyro_sw_set_spins(pyro_sw *h, const void *host, size_t bytes, int64_t next_s
     const size_t need = h->model == PYRO_ISING ? (size_t)h->N : sizeof(float) * h->model * (size_t)h->N;
     if (!host || bytes != need) return fail(PYRO_EINVAL, "host buffer size must equal the spin array size");
     if (next_sweep < 0 || next_sweep > (int64_t)UINT32_MAX) return fail(PYRO_EINVAL, "bad sweep index");
+    bool vacant = false;
     if (h->model == PYRO_ISING) {
         const int8_t *s = (const int8_t *)host;
-        for (int64_t i = 0; i < h->N; ++i)
-            if (s[i] != 1 && s[i] != -1) return fail(PYRO_EINVAL, "Ising spins must be +1 or -1");
+        for (int64_t i = 0; i < h->N; ++i) {
+            if (s[i] != 1 && s[i] != -1 && s[i] != 0) return fail(PYRO_EINVAL, "Ising spins must be +1, -1 or 0 (vacant)");
+            vacant |= s[i] == 0;
+        }
     }
     HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
+    if (vacant) {
+        std::vector<uint64_t> pm;
+        present_masks((const int8_t *)host, h->L, pm);
+        if (!h->d_present && hipMalloc((void **)&h->d_present, sizeof(uint64_t) * (size_t)h->ncell) != hipSuccess) {
+            (void)hipGetLastError();
+            h->d_present = nullptr;
+            return fail(PYRO_ENOMEM, "bond masks of a diluted lattice");
+        }
+        HIP_OR_FAIL(&h->broken, hipMemcpy(h->d_present, pm.data(), sizeof(uint64_t) * pm.size(), hipMemcpyHostToDevice));
+    }
+    h->diluted = vacant;
+    h->param_version++;  // descriptors (and captured sweeps) pick up the masks
     HIP_OR_FAIL(&h->broken, hipMemcpy(h->spins, host, need, hipMemcpyHostToDevice));
     h->hs = RepState{(uint32_t)next_sweep, 0, 0, -1};
     h->host_q.clear();
@@ -908,6 +956,7 @@ int pyro_sw_destroy(pyro_sw *h)
         hipFree(h->spins);
         hipFree(h->work);
     }
+    if (h->d_present) hipFree(h->d_present);
     if (h->own_stream) hipStreamDestroy(h->stream);
     delete h;
     return rc;
