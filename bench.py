@@ -339,6 +339,35 @@ def diluted_throughput(sweeps, stream, dev):
     return out
 
 
+def graph_throughput(sweeps, stream, dev):
+    """The generic graph path (any bond table): simple-cubic Ising L = 256 at
+    its T_c, and the pyrochlore L = 128 table at T = 4.2139 for comparison
+    with the tiled sweep; spin-updates/s after 10 warm-up sweeps."""
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    sc = workloads.SC_ISING_L256
+    cases = (("simple_cubic_L256", pyrosw.simple_cubic_bonds(sc["L"]), sc["L"] ** 3, sc["T"], sc["seed"]),
+             ("pyrochlore_L128", pyrosw.pyro_sw_bonds(128), 16 * 128 ** 3, 4.2139, 3))
+    out = {}
+    for name, bonds, n, T, seed in cases:
+        g = pyrosw.Graph(bonds, n, 1, T, seed=seed, device=dev, stream=stream)
+        g.sweep(10)
+        g.moments()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.sweep(sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = g.moments()
+        g.close()
+        out[name] = {"sites": n, "bonds": len(bonds[0]), "T": T, "spin_updates_per_s": n * sweeps / dt,
+                     "us_per_sweep": dt / sweeps * 1e6, "mean_m2": float(rec["m2"].mean())}
+    out.update(workload="ising_graph_path", sweeps=sweeps)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +383,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the job server")
     ap.add_argument("--serve-quantum-ms", type=float, default=20.0, help="lane quantum of the job server")
     ap.add_argument("--on-sweeps", type=int, default=500, help="sweeps of the XY and Heisenberg L=64 leg (0: skip)")
+    ap.add_argument("--graph-sweeps", type=int, default=200,
+                    help="sweeps of the generic graph-path leg (simple cubic L=256, pyrochlore L=128; 0: skip)")
     ap.add_argument("--diluted-sweeps", type=int, default=500,
                     help="sweeps of the site-diluted Ising L=128 leg and its pure twin (0: skip)")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter-collection workload and exit")
@@ -506,6 +537,9 @@ def main():
     if args.diluted_sweeps > 0:
         log(f"bench: site-diluted and pure Ising L=128, {args.diluted_sweeps} sweeps each")
         out["diluted"] = diluted_throughput(args.diluted_sweeps, stream, dev)
+    if args.graph_sweeps > 0:
+        log(f"bench: generic graph path, {args.graph_sweeps} sweeps per lattice")
+        out["graph"] = graph_throughput(args.graph_sweeps, stream, dev)
     if args.batch_sweeps > 0:
         log(f"bench: 96-replica batch, {args.batch_sweeps} sweeps, batched then plain")
         out["batched"] = batched_vs_plain(args.batch_sweeps, stream, dev)

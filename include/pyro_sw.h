@@ -326,6 +326,45 @@ int pyro_sw_server_destroy(pyro_sw_server *s);
  */
 int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls_per_second, uint32_t *fold);
 
+/*
+ * Generic lattices: the same Swendsen-Wang sweep on any graph supplied as a
+ * nearest-neighbour (bond) table, the generality the paper claims for its
+ * algorithm (Sec. 2 and Sec. 4).  Bond b joins sites bond_a[b] and
+ * bond_b[b]; its random draws are keyed by b and the sweep index exactly as
+ * bond b of the pyrochlore sweep, and flip coins by the cluster's smallest
+ * site, so the pyrochlore table of pyro_sw_bonds reproduces that sweep's
+ * trajectory bit for bit.  No tiles: one thread per bond or site, with the
+ * global union-find of the pyrochlore sweep; slower, for any lattice.
+ *   pyro_sw_graph_init     n_sites in [1, 2^31 - 1], n_bonds in [0, 2^33];
+ *                          ends in range and distinct (EINVAL otherwise);
+ *                          host arrays are copied, the caller keeps them;
+ *                          model, T, J, seed, start and stream as in
+ *                          pyro_sw_init.  One device allocation: 8 B per
+ *                          bond, spins, 4 B per site of labels (O(n): 4 more
+ *                          of projections), partials, a record ring.
+ *   pyro_sw_graph_sweep    enqueue n_sweeps sweeps (records drained to the
+ *                          host every 1024 sweeps).
+ *   pyro_sw_graph_moments, _get_spins, _set_spins, _get_labels,
+ *   _set_temperature, _destroy   as for a pyrochlore handle (spin layouts
+ *                          int8 [N] or float [n][N]; a zero spin is a vacant
+ *                          site; labels are the smallest site index of each
+ *                          site's cluster after the last sweep).
+ * pyro_sw_bonds writes the pyrochlore bond table of edge L (n = 48 L^3
+ * entries per array, bond 48 cell + 6 t + e as in the site numbering above)
+ * into host arrays.
+ */
+typedef struct pyro_sw_graph pyro_sw_graph;
+int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, const int32_t *bond_a,
+                       const int32_t *bond_b, int model, double T, double J, uint64_t seed, int start, void *stream);
+int pyro_sw_graph_sweep(pyro_sw_graph *g, int64_t n_sweeps);
+int pyro_sw_graph_moments(pyro_sw_graph *g, pyro_sw_record *out, int64_t cap, int64_t *n_out);
+int pyro_sw_graph_get_spins(pyro_sw_graph *g, void *host, size_t bytes);
+int pyro_sw_graph_set_spins(pyro_sw_graph *g, const void *host, size_t bytes, int64_t next_sweep);
+int pyro_sw_graph_get_labels(pyro_sw_graph *g, int32_t *host, size_t n);
+int pyro_sw_graph_set_temperature(pyro_sw_graph *g, double T);
+int pyro_sw_graph_destroy(pyro_sw_graph *g);
+int pyro_sw_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n);
+
 /* Synchronise and free everything the library allocated.  NULL is a no-op. */
 int pyro_sw_destroy(pyro_sw *h);
 

@@ -1,0 +1,554 @@
+// Swendsen-Wang sweep on any graph given as a bond list (nearest-neighbour
+// table): the paper's remark that the algorithm carries over to other
+// lattices once a nearest-neighbour table is supplied (Sec. 2, Sec. 4).
+//
+// No tiles: one thread per bond or per site.  Per sweep:
+//   O(n) only  k_graph_axis       embedding axis of the sweep (one thread)
+//              k_graph_prepare    label[i] = i; O(n): sigma_i = s_i . r
+//              k_graph_bonds      activation of each bond, and union of its two
+//                                 sites in the global forest (index linking:
+//                                 the larger root is hooked under the smaller
+//                                 by compare-and-swap, so every tree root is
+//                                 its cluster's smallest site)
+//              k_graph_flip       root of each site (pointer chase, written
+//                                 back), flip coin of the root, flip or
+//                                 reflection, magnetisation partials
+//              k_graph_energy     bond sums of the new state, partials
+//              k_graph_finalize   fixed-order sums into the sweep's record
+// Random numbers, thresholds and FP32 operation order are those of the
+// pyrochlore sweep with bond b = position in the list and site i = index:
+//   Ising: r32(b) = byte (b mod 16) of Philox(b/16, t, BOND) << 24 | low 24
+//          bits of word (b mod 4) of Philox(b/4, t, BOND_LO); active iff the
+//          spins are equal and nonzero and r32 < thr;
+//   O(n):  r32(b) = word (b mod 4) of Philox(b/4, t, BOND);
+//   coin:  bit (r mod 32) of word ((r/32) mod 4) of Philox(r/128, t, FLIP).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pyro_sw.h"
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "on_bond.hpp"
+#include "philox.hpp"
+#include "unit_vector.hpp"
+
+namespace pyro {
+namespace {
+
+constexpr int kGraphRing = 1024;  // device records between drains
+
+struct GraphDesc {
+    int64_t N, NB;
+    int n;  // 1 Ising, 2 XY, 3 Heisenberg
+    const int32_t *ba, *bb;
+    void *spins;  // int8 [N] or float [n][N]
+    int32_t *label;
+    float *sigma;  // O(n) projections [N]
+    float *axis;   // [4]
+    int64_t *ipart;  // Ising partials: [bond blocks] then [site blocks]
+    double *dpart;   // O(n) partials: [bond blocks] then [3][site blocks]
+    DevRecord *ring;
+    uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
+    float x0;
+    double J;
+    PhiloxKey key;
+};
+
+__device__ __forceinline__ int32_t lab_get(const int32_t *lab, int32_t x)
+{
+    return __hip_atomic_load(const_cast<int32_t *>(lab) + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x: parents are never larger than their children, so the chase
+// ends.  Read only: in the flip pass every thread writes only its own site's
+// entry, so the final labels are all roots.  (Halving the path during the
+// union pass was measured slower: its extra stores cost more than the
+// shorter chases save.)
+__device__ __forceinline__ int32_t graph_root(const int32_t *lab, int32_t x)
+{
+    for (;;) {
+        const int32_t p = lab_get(lab, x);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+__device__ void graph_unite(int32_t *lab, int32_t a, int32_t b)
+{
+    for (;;) {
+        a = graph_root(lab, a);
+        b = graph_root(lab, b);
+        if (a == b) return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        int32_t expected = a;
+        if (__hip_atomic_compare_exchange_strong(lab + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        a = expected;  // hooked meanwhile: continue from its new parent
+    }
+}
+
+__device__ __forceinline__ uint32_t coin_of(int32_t r, uint32_t t, PhiloxKey key)
+{
+    const uint4 w = philox4x32_10((uint32_t)r >> 7, t, kStreamFlip, 0u, key);
+    return (word_of(w, ((uint32_t)r >> 5) & 3u) >> (r & 31)) & 1u;
+}
+
+__global__ void k_graph_axis(GraphDesc g, uint32_t t)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float r[3];
+    unit_vector(0u, t, kStreamAxis, g.n, g.key, r);
+    g.axis[0] = r[0];
+    g.axis[1] = r[1];
+    g.axis[2] = r[2];
+    g.axis[3] = 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_prepare(GraphDesc g)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.N) return;
+    g.label[i] = (int32_t)i;
+    if (g.n == 1) return;
+    const float *s = (const float *)g.spins;
+    const float r[3] = {g.axis[0], g.axis[1], g.axis[2]};
+    const float v[3] = {s[i], s[g.N + i], g.n == 3 ? s[2 * g.N + i] : 0.0f};
+    g.sigma[i] = g.n == 2 ? project<2>(v, r) : project<3>(v, r);
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_bonds(GraphDesc g, uint32_t t)
+{
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b >= g.NB) return;
+    const int32_t i = g.ba[b], j = g.bb[b];
+    bool active;
+    if (g.n == 1) {
+        const int8_t *s = (const int8_t *)g.spins;
+        const int8_t si = s[i], sj = s[j];
+        active = false;
+        if (si == sj && si != 0) {
+            const uint4 w = philox4x32_10((uint32_t)(b >> 4), t, kStreamBond, 0u, g.key);
+            const uint32_t k = (uint32_t)b & 15u;
+            const uint32_t hi = (word_of(w, k >> 2) >> (8 * (k & 3u))) & 0xFFu;
+            if (hi != g.thr_hi) {
+                active = hi < g.thr_hi;
+            } else {
+                const uint4 v = philox4x32_10((uint32_t)(b >> 2), t, kStreamBondLo, 0u, g.key);
+                active = (word_of(v, (uint32_t)b & 3u) & 0xFFFFFFu) < g.thr_lo;
+            }
+        }
+    } else {
+        const float x = __fmul_rn(__fmul_rn(g.x0, g.sigma[i]), g.sigma[j]);
+        const uint4 w = philox4x32_10((uint32_t)(b >> 2), t, kStreamBond, 0u, g.key);
+        active = on_bond_active(x, word_of(w, (uint32_t)b & 3u));
+    }
+    if (active) graph_unite(g.label, i, j);
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t, int64_t site_off)
+{
+    __shared__ int64_t ired[16];
+    __shared__ double dred[16];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t m = 0;
+    double mv[3] = {0.0, 0.0, 0.0};
+    if (i < g.N) {
+        const int32_t r = graph_root(g.label, (int32_t)i);
+        g.label[i] = r;
+        const uint32_t c = coin_of(r, t, g.key);
+        if (g.n == 1) {
+            int8_t *s = (int8_t *)g.spins;
+            int8_t v = s[i];
+            if (c) {
+                v = (int8_t)-v;
+                s[i] = v;
+            }
+            m = v;
+        } else {
+            float *s = (float *)g.spins;
+            const float cf = __fmul_rn(-2.0f, g.sigma[i]);
+            for (int k = 0; k < g.n; ++k) {
+                float v = s[(int64_t)k * g.N + i];
+                if (c) {
+                    v = __fmaf_rn(cf, g.axis[k], v);
+                    s[(int64_t)k * g.N + i] = v;
+                }
+                mv[k] = (double)v;
+            }
+        }
+    }
+    const int64_t nsb = blocks_for(g.N);
+    if (g.n == 1) {
+        const int64_t bs = block_sum<int64_t>(m, ired);
+        if (threadIdx.x == 0) g.ipart[site_off + blockIdx.x] = bs;
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            const double bs = block_sum<double>(mv[k], dred);
+            if (threadIdx.x == 0) g.dpart[site_off + k * nsb + blockIdx.x] = bs;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_energy(GraphDesc g)
+{
+    __shared__ int64_t ired[16];
+    __shared__ double dred[16];
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g.n == 1) {
+        int64_t e = 0;
+        if (b < g.NB) {
+            const int8_t *s = (const int8_t *)g.spins;
+            e = (int64_t)s[g.ba[b]] * (int64_t)s[g.bb[b]];
+        }
+        const int64_t bs = block_sum<int64_t>(e, ired);
+        if (threadIdx.x == 0) g.ipart[blockIdx.x] = bs;
+    } else {
+        double e = 0.0;
+        if (b < g.NB) {
+            const float *s = (const float *)g.spins;
+            const int32_t i = g.ba[b], j = g.bb[b];
+            for (int k = 0; k < g.n; ++k) e += (double)s[(int64_t)k * g.N + i] * (double)s[(int64_t)k * g.N + j];
+        }
+        const double bs = block_sum<double>(e, dred);
+        if (threadIdx.x == 0) g.dpart[blockIdx.x] = bs;
+    }
+}
+
+// Partials: bond-block sums at [0, nbb), site-block sums from site_off on.
+__global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t t, int slot, int64_t nbb,
+                                                           int64_t site_off)
+{
+    __shared__ int64_t ired[16];
+    __shared__ double dred[16];
+    const int64_t nsb = blocks_for(g.N);
+    DevRecord r{};
+    r.sweep = t;
+    if (g.n == 1) {
+        int64_t E = 0, M = 0;
+        for (int64_t k = threadIdx.x; k < nbb; k += kBlock) E += g.ipart[k];
+        for (int64_t k = threadIdx.x; k < nsb; k += kBlock) M += g.ipart[site_off + k];
+        E = block_sum<int64_t>(E, ired);
+        M = block_sum<int64_t>(M, ired);
+        if (threadIdx.x == 0) {
+            r.bond_sum = E;
+            r.M_int = M;
+            r.E = -g.J * (double)E;
+            r.M[0] = (double)M;
+            const double mm = (double)M / (double)g.N;
+            r.m2 = mm * mm;
+            r.m4 = r.m2 * r.m2;
+            g.ring[slot] = r;
+        }
+    } else {
+        double S = 0.0, M[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = threadIdx.x; k < nbb; k += kBlock) S += g.dpart[k];
+        for (int c = 0; c < 3; ++c)
+            for (int64_t k = threadIdx.x; k < nsb; k += kBlock) M[c] += g.dpart[site_off + c * nsb + k];
+        S = block_sum<double>(S, dred);
+        for (int c = 0; c < 3; ++c) M[c] = block_sum<double>(M[c], dred);
+        if (threadIdx.x == 0) {
+            r.E = -g.J * S;
+            r.M[0] = M[0];
+            r.M[1] = M[1];
+            r.M[2] = M[2];
+            const double mm = sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]) / (double)g.N;
+            r.m2 = mm * mm;
+            r.m4 = r.m2 * r.m2;
+            g.ring[slot] = r;
+        }
+    }
+}
+
+hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStream_t st)
+{
+    const int nsb = blocks_for(g.N), nbb = blocks_for(g.NB);
+    const int64_t site_off = std::max(nbb, 1);  // as sized at init
+    if (g.n > 1) k_graph_axis<<<1, 64, 0, st>>>(g, t);
+    k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
+    if (nbb > 0) k_graph_bonds<<<nbb, kBlock, 0, st>>>(g, t);
+    k_graph_flip<<<nsb, kBlock, 0, st>>>(g, t, site_off);
+    if (nbb > 0) k_graph_energy<<<nbb, kBlock, 0, st>>>(g);
+    k_graph_finalize<<<1, kBlock, 0, st>>>(g, t, slot, (int64_t)nbb, site_off);
+    return hipGetLastError();
+}
+
+int gfail(int status, const std::string &msg) { return record_error(status, msg.c_str()); }
+
+}  // namespace
+}  // namespace pyro
+
+using namespace pyro;
+
+struct pyro_sw_graph {
+    int model = 0;
+    int64_t N = 0, NB = 0;
+    double T = 0, J = 0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false, broken = false;
+    char *mem = nullptr;  // one device allocation for everything
+    GraphDesc d{};
+    uint32_t t = 0;       // global index of the next sweep
+    int ring_used = 0;
+    std::deque<pyro_sw_record> host_q;
+};
+
+namespace {
+
+int gdevice(pyro_sw_graph *g, hipError_t e, const char *what)
+{
+    g->broken = true;
+    (void)hipGetLastError();
+    return gfail(PYRO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GHIP(call)                                       \
+    do {                                                 \
+        hipError_t e__ = (call);                         \
+        if (e__ != hipSuccess) return gdevice(g, e__, #call); \
+    } while (0)
+
+int gusable(const pyro_sw_graph *g)
+{
+    if (!g) return gfail(PYRO_EINVAL, "graph is NULL");
+    if (g->broken) return gfail(PYRO_ESTATE, "graph had a device error");
+    return PYRO_OK;
+}
+
+void graph_params(pyro_sw_graph *g, double T)
+{
+    g->T = T;
+    const double twobj = 2.0 * g->J / T;
+    const uint64_t thr = (uint64_t)floor(-expm1(-twobj) * 4294967296.0);
+    g->d.thr_hi = (uint32_t)(thr >> 24);
+    g->d.thr_lo = (uint32_t)(thr & 0xFFFFFFu);
+    g->d.x0 = (float)twobj;
+}
+
+int graph_drain(pyro_sw_graph *g)
+{
+    if (g->ring_used == 0) return PYRO_OK;
+    std::vector<pyro_sw_record> tmp((size_t)g->ring_used);
+    GHIP(hipStreamSynchronize(g->stream));
+    GHIP(hipMemcpy(tmp.data(), g->d.ring, sizeof(DevRecord) * tmp.size(), hipMemcpyDeviceToHost));
+    for (const auto &r : tmp) g->host_q.push_back(r);
+    g->ring_used = 0;
+    return PYRO_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, const int32_t *bond_a,
+                       const int32_t *bond_b, int model, double T, double J, uint64_t seed, int start, void *stream)
+{
+    if (!out) return gfail(PYRO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_sites < 1 || n_sites > (int64_t)INT32_MAX) return gfail(PYRO_EINVAL, "n_sites must be in [1, 2^31 - 1]");
+    if (n_bonds < 0 || n_bonds > ((int64_t)1 << 33)) return gfail(PYRO_EINVAL, "n_bonds must be in [0, 2^33]");
+    if (n_bonds > 0 && (!bond_a || !bond_b)) return gfail(PYRO_EINVAL, "bond lists are NULL");
+    if (model < PYRO_ISING || model > PYRO_HEISENBERG) return gfail(PYRO_EINVAL, "model must be 1, 2 or 3");
+    if (!(T > 0.0)) return gfail(PYRO_EINVAL, "T must be > 0 (inf allowed)");
+    if (!(J > 0.0) || isinf(J)) return gfail(PYRO_EINVAL, "J must be finite and > 0");
+    if (start != PYRO_START_COLD && start != PYRO_START_RANDOM)
+        return gfail(PYRO_EINVAL, "start must be PYRO_START_COLD or PYRO_START_RANDOM");
+    for (int64_t k = 0; k < n_bonds; ++k)
+        if (bond_a[k] < 0 || bond_a[k] >= n_sites || bond_b[k] < 0 || bond_b[k] >= n_sites || bond_a[k] == bond_b[k])
+            return gfail(PYRO_EINVAL, "bond " + std::to_string(k) + " has an end out of range or joins a site to itself");
+    pyro_sw_graph *g = new (std::nothrow) pyro_sw_graph();
+    if (!g) return gfail(PYRO_ENOMEM, "graph handle");
+    g->model = model;
+    g->N = n_sites;
+    g->NB = n_bonds;
+    g->J = J;
+    g->seed = seed;
+    const int64_t nsb = blocks_for(n_sites), nbb = std::max<int64_t>(blocks_for(n_bonds), 1);
+    const size_t spin_bytes = model == PYRO_ISING ? (size_t)n_sites : sizeof(float) * model * (size_t)n_sites;
+    size_t off[9], total = 0;
+    const size_t sizes[9] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
+                             sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
+                             16, sizeof(int64_t) * (size_t)(nbb + nsb), sizeof(double) * (size_t)(nbb + 3 * nsb),
+                             sizeof(DevRecord) * kGraphRing};
+    for (int k = 0; k < 9; ++k) {
+        off[k] = total;
+        total += align256(sizes[k]);
+    }
+    if (stream) {
+        g->stream = (hipStream_t)stream;
+    } else {
+        const hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete g;
+            return gfail(PYRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        g->own_stream = true;
+    }
+    if (hipMalloc((void **)&g->mem, total) != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->own_stream) hipStreamDestroy(g->stream);
+        delete g;
+        return gfail(PYRO_ENOMEM, "graph device memory");
+    }
+    GraphDesc &d = g->d;
+    d.N = n_sites;
+    d.NB = n_bonds;
+    d.n = model;
+    d.ba = (const int32_t *)(g->mem + off[0]);
+    d.bb = (const int32_t *)(g->mem + off[1]);
+    d.spins = g->mem + off[2];
+    d.label = (int32_t *)(g->mem + off[3]);
+    d.sigma = model == PYRO_ISING ? nullptr : (float *)(g->mem + off[4]);
+    d.axis = (float *)(g->mem + off[5]);
+    d.ipart = (int64_t *)(g->mem + off[6]);
+    d.dpart = (double *)(g->mem + off[7]);
+    d.ring = (DevRecord *)(g->mem + off[8]);
+    d.J = J;
+    d.key = philox_key(seed);
+    graph_params(g, T);
+    *out = g;
+    if (n_bonds > 0) {
+        GHIP(hipMemcpy((void *)d.ba, bond_a, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice));
+        GHIP(hipMemcpy((void *)d.bb, bond_b, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice));
+    }
+    RepDesc rd{};
+    rd.N = n_sites;
+    rd.spins = d.spins;
+    rd.label = d.label;
+    rd.key = d.key;
+    GHIP(launch_init(rd, model, start, g->stream));
+    GHIP(hipStreamSynchronize(g->stream));
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_sweep(pyro_sw_graph *g, int64_t n_sweeps)
+{
+    int rc = gusable(g);
+    if (rc) return rc;
+    if (n_sweeps < 0) return gfail(PYRO_EINVAL, "n_sweeps must be >= 0");
+    if ((int64_t)g->t + n_sweeps > (int64_t)UINT32_MAX) return gfail(PYRO_EINVAL, "sweep index would pass 2^32 - 1");
+    for (int64_t k = 0; k < n_sweeps; ++k) {
+        if (g->ring_used == kGraphRing && (rc = graph_drain(g))) return rc;
+        GHIP(launch_graph_sweep(g->d, g->t, g->ring_used, g->stream));
+        ++g->ring_used;
+        ++g->t;
+    }
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_moments(pyro_sw_graph *g, pyro_sw_record *out, int64_t cap, int64_t *n_out)
+{
+    int rc = gusable(g);
+    if (rc) return rc;
+    if (!n_out || cap < 0 || (cap > 0 && !out)) return gfail(PYRO_EINVAL, "bad output arguments");
+    if ((rc = graph_drain(g))) return rc;
+    GHIP(hipStreamSynchronize(g->stream));
+    int64_t n = 0;
+    if (cap == 0) {
+        *n_out = (int64_t)g->host_q.size();
+        return PYRO_OK;
+    }
+    while (n < cap && !g->host_q.empty()) {
+        out[n++] = g->host_q.front();
+        g->host_q.pop_front();
+    }
+    *n_out = n;
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_get_spins(pyro_sw_graph *g, void *host, size_t bytes)
+{
+    int rc = gusable(g);
+    if (rc) return rc;
+    const size_t need = g->model == PYRO_ISING ? (size_t)g->N : sizeof(float) * g->model * (size_t)g->N;
+    if (!host || bytes != need) return gfail(PYRO_EINVAL, "host buffer size must equal the spin array size");
+    GHIP(hipStreamSynchronize(g->stream));
+    GHIP(hipMemcpy(host, g->d.spins, need, hipMemcpyDeviceToHost));
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_set_spins(pyro_sw_graph *g, const void *host, size_t bytes, int64_t next_sweep)
+{
+    int rc = gusable(g);
+    if (rc) return rc;
+    const size_t need = g->model == PYRO_ISING ? (size_t)g->N : sizeof(float) * g->model * (size_t)g->N;
+    if (!host || bytes != need) return gfail(PYRO_EINVAL, "host buffer size must equal the spin array size");
+    if (next_sweep < 0 || next_sweep > (int64_t)UINT32_MAX) return gfail(PYRO_EINVAL, "bad sweep index");
+    if (g->model == PYRO_ISING) {
+        const int8_t *s = (const int8_t *)host;
+        for (int64_t i = 0; i < g->N; ++i)
+            if (s[i] != 1 && s[i] != -1 && s[i] != 0) return gfail(PYRO_EINVAL, "Ising spins must be +1, -1 or 0 (vacant)");
+    }
+    GHIP(hipStreamSynchronize(g->stream));
+    GHIP(hipMemcpy(g->d.spins, host, need, hipMemcpyHostToDevice));
+    g->t = (uint32_t)next_sweep;
+    g->ring_used = 0;
+    g->host_q.clear();
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_get_labels(pyro_sw_graph *g, int32_t *host, size_t n)
+{
+    int rc = gusable(g);
+    if (rc) return rc;
+    if (!host || n != (size_t)g->N) return gfail(PYRO_EINVAL, "n must equal the number of sites");
+    GHIP(hipStreamSynchronize(g->stream));
+    GHIP(hipMemcpy(host, g->d.label, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_set_temperature(pyro_sw_graph *g, double T)
+{
+    int rc = gusable(g);
+    if (rc) return rc;
+    if (!(T > 0.0)) return gfail(PYRO_EINVAL, "T must be > 0 (inf allowed)");
+    GHIP(hipStreamSynchronize(g->stream));
+    graph_params(g, T);
+    return PYRO_OK;
+}
+
+int pyro_sw_graph_destroy(pyro_sw_graph *g)
+{
+    if (!g) return PYRO_OK;
+    int rc = PYRO_OK;
+    if (g->stream && hipStreamSynchronize(g->stream) != hipSuccess) rc = gfail(PYRO_EDEVICE, "synchronize failed");
+    hipFree(g->mem);
+    if (g->own_stream) hipStreamDestroy(g->stream);
+    delete g;
+    return rc;
+}
+
+int pyro_sw_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n)
+{
+    if (L < 1 || L > 406) return gfail(PYRO_EINVAL, "L must be in [1, 406]");
+    if (!bond_a || !bond_b || n != 48 * (int64_t)L * L * L) return gfail(PYRO_EINVAL, "n must equal 48 L^3");
+    const int64_t nc = (int64_t)L * L * L;
+    for (int64_t c = 0; c < nc; ++c) {
+        const CellNbrs nb = cell_neighbours((int)c, L);
+        for (int j = 0; j < 48; ++j) {
+            const SiteRef a = bond_end_a(j), b = bond_end_b(j);
+            bond_a[48 * c + j] = 16 * nb.c[a.cell] + a.site;
+            bond_b[48 * c + j] = 16 * nb.c[b.cell] + b.site;
+        }
+    }
+    return PYRO_OK;
+}
+
+}  // extern "C"

@@ -62,7 +62,7 @@ struct CellNbrs {
     int c[kNCellCodes];
 };
 
-__device__ __forceinline__ CellNbrs cell_neighbours(int cell, int L)
+__host__ __device__ __forceinline__ CellNbrs cell_neighbours(int cell, int L)
 {
     const int x = cell % L;
     const int y = (cell / L) % L;

@@ -26,6 +26,7 @@
 #include "ising_cell.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "on_bond.hpp"
 #include "philox.hpp"
 #include "tile_common.hpp"
 #include "unit_vector.hpp"
@@ -47,32 +48,6 @@ __global__ void k_axis(Chain c)
     d.axis[3] = 0.0f;
 }
 
-template <int NV>
-__device__ __forceinline__ float project(const float v[NV], const float r[NV])
-{
-    float sig = __fmul_rn(v[0], r[0]);
-    sig = __fmaf_rn(v[1], r[1], sig);
-    if (NV == 3) sig = __fmaf_rn(v[NV - 1], r[NV - 1], sig);
-    return sig;
-}
-
-// The exact comparison, out of line: it is rarely reached, and 48 inlined
-// copies per cell would swell the tile kernel's code.
-__device__ __noinline__ bool on_bond_exact(float x, double u) { return (double)x > -log1p(-u); }
-
-// Exact activation decision of one bond (see the file comment).  1 - u is
-// exact in FP64 and at least 2^-33, so its FP32 rounding is a normal number
-// within a relative 2^-24.
-__device__ __forceinline__ bool on_bond_active(float x, uint32_t r32)
-{
-    if (!(x > 0.0f)) return false;
-    const double u = ((double)r32 + 0.5) * 0x1p-32;
-    const float t = -0.6931472f * __log2f((float)(1.0 - u));  // native base-2 logarithm
-    const float m = 1e-4f * (1.0f + t);
-    if (x > t + m) return true;
-    if (x < t - m) return false;
-    return on_bond_exact(x, u);
-}
 
 template <int NV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)

@@ -319,20 +319,12 @@ void present_masks(const int8_t *s, int L, std::vector<uint64_t> &pm)
     const int64_t nc = (int64_t)L * L * L;
     pm.assign((size_t)nc, 0);
     for (int64_t c = 0; c < nc; ++c) {
-        const int x = (int)(c % L), y = (int)((c / L) % L), z = (int)(c / ((int64_t)L * L));
-        const int xm = x == 0 ? L - 1 : x - 1, ym = y == 0 ? L - 1 : y - 1, zm = z == 0 ? L - 1 : z - 1;
-        int64_t nb[kNCellCodes];
-        nb[kSelf] = c;
-        nb[kMx] = ((int64_t)z * L + y) * L + xm;
-        nb[kMy] = ((int64_t)z * L + ym) * L + x;
-        nb[kMz] = ((int64_t)zm * L + y) * L + x;
-        nb[kMyMz] = ((int64_t)zm * L + ym) * L + x;
-        nb[kMxMz] = ((int64_t)zm * L + y) * L + xm;
-        nb[kMxMy] = ((int64_t)z * L + ym) * L + xm;
+        const CellNbrs nb = cell_neighbours((int)c, L);
         uint64_t m = 0;
         for (int j = 0; j < 48; ++j) {
             const SiteRef a = bond_end_a(j), b = bond_end_b(j);
-            if (s[16 * nb[a.cell] + a.site] != 0 && s[16 * nb[b.cell] + b.site] != 0) m |= 1ull << j;
+            if (s[16 * (int64_t)nb.c[a.cell] + a.site] != 0 && s[16 * (int64_t)nb.c[b.cell] + b.site] != 0)
+                m |= 1ull << j;
         }
         pm[(size_t)c] = m;
     }

@@ -48,6 +48,9 @@ EXPORTS = (
     "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
     "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
     "pyro_sw_philox_rate",
+    "pyro_sw_graph_init", "pyro_sw_graph_sweep", "pyro_sw_graph_moments", "pyro_sw_graph_get_spins",
+    "pyro_sw_graph_set_spins", "pyro_sw_graph_get_labels", "pyro_sw_graph_set_temperature",
+    "pyro_sw_graph_destroy", "pyro_sw_bonds",
 )
 
 PYRO_JOB_QUEUED, PYRO_JOB_RUNNING, PYRO_JOB_DONE = 0, 1, 2
@@ -89,6 +92,12 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                            "(run python -m paper_1612_08312_amd.build)")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading it
+    # first makes the library bind to that one, so that the library and
+    # PyTorch share one runtime and one device context; loaded the other way
+    # round, the library's first stream creation has reported no device.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, u64, i32, f64, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int,
                                   ctypes.c_double, ctypes.c_size_t)
@@ -124,6 +133,15 @@ def load_library():
     lib.pyro_sw_server_take.argtypes = [vp, i64, vp, i64, P(i64), vp, sz]
     lib.pyro_sw_server_clock.argtypes = [vp, P(f64)]
     lib.pyro_sw_server_destroy.argtypes = [vp]
+    lib.pyro_sw_graph_init.argtypes = [P(vp), i64, i64, vp, vp, i32, f64, f64, u64, i32, vp]
+    lib.pyro_sw_graph_sweep.argtypes = [vp, i64]
+    lib.pyro_sw_graph_moments.argtypes = [vp, vp, i64, P(i64)]
+    lib.pyro_sw_graph_get_spins.argtypes = [vp, vp, sz]
+    lib.pyro_sw_graph_set_spins.argtypes = [vp, vp, sz, i64]
+    lib.pyro_sw_graph_get_labels.argtypes = [vp, vp, sz]
+    lib.pyro_sw_graph_set_temperature.argtypes = [vp, f64]
+    lib.pyro_sw_graph_destroy.argtypes = [vp]
+    lib.pyro_sw_bonds.argtypes = [i32, vp, vp, i64]
     lib.pyro_sw_strerror.argtypes = [i32]
     lib.pyro_sw_strerror.restype = ctypes.c_char_p
     lib.pyro_sw_last_error.argtypes = []
@@ -512,3 +530,102 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------- graphs --
+
+
+def pyro_sw_bonds(L: int):
+    """Pyrochlore bond table of edge L: (bond_a, bond_b), int32 [48 L^3]."""
+    n = 48 * int(L) ** 3
+    a = np.zeros(n, np.int32)
+    b = np.zeros(n, np.int32)
+    _check(load_library().pyro_sw_bonds(int(L), a.ctypes.data_as(ctypes.c_void_p),
+                                        b.ctypes.data_as(ctypes.c_void_p), n), "pyro_sw_bonds")
+    return a, b
+
+
+def simple_cubic_bonds(L: int):
+    """Simple-cubic bond table of edge L, periodic: site (z L + y) L + x, bond
+    3 i + d to its +x, +y, +z neighbour (d = 0, 1, 2)."""
+    L = int(L)
+    i = np.arange(L ** 3, dtype=np.int64)
+    x, y, z = i % L, (i // L) % L, i // (L * L)
+    nb = np.stack([(z * L + y) * L + (x + 1) % L,
+                   (z * L + (y + 1) % L) * L + x,
+                   (((z + 1) % L) * L + y) * L + x], axis=1)
+    a = np.repeat(i, 3).astype(np.int32)
+    return a, nb.reshape(-1).astype(np.int32)
+
+
+class Graph:
+    """One lattice given by its bond table, swept by the generic graph path
+    (any nearest-neighbour table; see pyro_sw_graph_init)."""
+
+    def __init__(self, bonds, n_sites, model, T, J=1.0, seed=1, start=PYRO_START_RANDOM, device="cuda:0",
+                 stream=None):
+        import torch
+
+        lib = load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        a = np.ascontiguousarray(bonds[0], dtype=np.int32)
+        b = np.ascontiguousarray(bonds[1], dtype=np.int32)
+        if a.shape != b.shape:
+            raise ValueError("bond arrays differ in length")
+        self.model, self.N, self.NB = model, int(n_sites), len(a)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.pyro_sw_graph_init(ctypes.byref(h), self.N, self.NB, a.ctypes.data_as(ctypes.c_void_p),
+                                          b.ctypes.data_as(ctypes.c_void_p), int(model), float(T), float(J),
+                                          int(seed), int(start), _stream_ptr(self.stream)),
+                   "pyro_sw_graph_init")
+        self.g = h
+
+    def sweep(self, n=1):
+        _check(load_library().pyro_sw_graph_sweep(self.g, int(n)), "pyro_sw_graph_sweep")
+
+    def moments(self) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_int64()
+        _check(lib.pyro_sw_graph_moments(self.g, None, 0, ctypes.byref(n)), "pyro_sw_graph_moments")
+        out = np.zeros(n.value, dtype=RECORD_DTYPE)
+        if n.value:
+            _check(lib.pyro_sw_graph_moments(self.g, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                             ctypes.byref(n)), "pyro_sw_graph_moments")
+        return out[: n.value]
+
+    def spins(self) -> np.ndarray:
+        out = np.zeros(self.N, np.int8) if self.model == PYRO_ISING else np.zeros((self.model, self.N), np.float32)
+        _check(load_library().pyro_sw_graph_get_spins(self.g, out.ctypes.data_as(ctypes.c_void_p), out.nbytes),
+               "pyro_sw_graph_get_spins")
+        return out
+
+    def set_spins(self, s, next_sweep):
+        a = np.ascontiguousarray(s)
+        _check(load_library().pyro_sw_graph_set_spins(self.g, a.ctypes.data_as(ctypes.c_void_p), a.nbytes,
+                                                      int(next_sweep)), "pyro_sw_graph_set_spins")
+
+    def labels(self) -> np.ndarray:
+        out = np.zeros(self.N, np.int32)
+        _check(load_library().pyro_sw_graph_get_labels(self.g, out.ctypes.data_as(ctypes.c_void_p), self.N),
+               "pyro_sw_graph_get_labels")
+        return out
+
+    def set_temperature(self, T):
+        _check(load_library().pyro_sw_graph_set_temperature(self.g, float(T)), "pyro_sw_graph_set_temperature")
+
+    def close(self):
+        if getattr(self, "g", None) is not None:
+            pyro_sw_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pyro_sw_graph_destroy(g):
+    _check(load_library().pyro_sw_graph_destroy(g), "pyro_sw_graph_destroy")

@@ -114,3 +114,8 @@ def diluted_spins(N: int, model: int, vacancy: float, seed: int) -> np.ndarray:
 # Site-diluted Ising lattice: L = 128, 10% vacant sites, T = 3.8 (the pure
 # lattice orders there, T_c = 4.21394; the diluted one does not).
 DILUTED_ISING_L128 = dict(L=128, model=ISING, T=3.8, J=1.0, seed=7, vacancy=0.1)
+
+# Simple-cubic Ising lattice for the generic graph path: L = 256
+# (16,777,216 sites, 3 bonds per site) at the simple-cubic T_c the paper
+# quotes (Sec. 3.1), random start.
+SC_ISING_L256 = dict(L=256, model=ISING, T=4.511524, J=1.0, seed=3)

@@ -105,3 +105,43 @@ def test_philox_rate_rejects_bad_arguments_without_a_device(calls, repeats):
 def test_philox_rate_null_outputs():
     lib = pyrosw.load_library()
     assert lib.pyro_sw_philox_rate(16, 1, 1, None, None) == pyrosw.PYRO_EINVAL
+
+
+def test_bond_tables_match_the_oracle():
+    """pyro_sw_bonds (host code of the library) and the package's simple-cubic
+    table give the oracle's bond lists, bond for bond."""
+    import numpy as np
+
+    import oracle
+
+    for L in (1, 2, 3, 5):
+        a, b = pyrosw.pyro_sw_bonds(L)
+        oa, ob = oracle.Oracle(L=L).bonds()
+        np.testing.assert_array_equal(a, oa)
+        np.testing.assert_array_equal(b, ob)
+    for L in (2, 3, 6):
+        a, b = pyrosw.simple_cubic_bonds(L)
+        oa, ob = oracle.Oracle(L=L, lattice="sc").bonds()
+        np.testing.assert_array_equal(a, oa)
+        np.testing.assert_array_equal(b, ob)
+    with pytest.raises(pyrosw.PyroSWError):
+        pyrosw.pyro_sw_bonds(0)
+
+
+@pytest.mark.parametrize("bonds,n,model", [
+    (([0], [0]), 4, 1),      # a site joined to itself
+    (([0], [4]), 4, 1),      # an end out of range
+    (([-1], [2]), 4, 1),
+    (([0], [1]), 0, 1),      # no sites
+    (([0], [1]), 4, 5),      # bad model
+])
+def test_graph_init_rejects_bad_arguments_without_a_device(bonds, n, model):
+    import numpy as np
+
+    lib = pyrosw.load_library()
+    a = np.asarray(bonds[0], np.int32)
+    b = np.asarray(bonds[1], np.int32)
+    h = ctypes.c_void_p()
+    rc = lib.pyro_sw_graph_init(ctypes.byref(h), n, len(a), a.ctypes.data_as(ctypes.c_void_p),
+                                b.ctypes.data_as(ctypes.c_void_p), model, 4.0, 1.0, 1, 0, None)
+    assert rc == pyrosw.PYRO_EINVAL and not h.value

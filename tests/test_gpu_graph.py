@@ -1,0 +1,113 @@
+"""The generic graph path (any nearest-neighbour table; Sec. 2 and Sec. 4 of
+the paper) on the GPU against the oracle: the pyrochlore table of
+pyro_sw_bonds reproduces the oracle's pyrochlore trajectory, the simple-cubic
+table the oracle's simple-cubic one, and a random graph the oracle's
+edge-list mode.  Ising: records, spins and labels bit for bit; O(n): spins
+and labels bit for bit, records within 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_08312_amd import pyrosw, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def compare(g, o, sweeps, model, chunks=2):
+    gr, orr = [], []
+    for _ in range(chunks):
+        g.sweep(sweeps // chunks)
+        gr.append(g.moments())
+        orr.append(o.sweep(sweeps // chunks))
+    gr, orr = np.concatenate(gr), np.concatenate(orr)
+    assert len(gr) == len(orr) == sweeps
+    np.testing.assert_array_equal(g.spins(), o.spins())
+    np.testing.assert_array_equal(g.labels(), o.labels())
+    np.testing.assert_array_equal(gr["sweep"], orr["sweep"])
+    if model == 1:
+        for f in ("bond_sum", "M_int", "E", "m2", "m4"):
+            np.testing.assert_array_equal(gr[f], orr[f], err_msg=f)
+    else:
+        np.testing.assert_allclose(gr["E"], orr["E"], rtol=1e-5, atol=1e-9)
+        np.testing.assert_allclose(gr["m2"], orr["m2"], rtol=1e-5, atol=1e-12)
+
+
+@pytest.mark.parametrize("model,L,T", [(1, 3, 4.2139), (1, 5, 4.0), (2, 3, 2.0285), (3, 4, 1.31695)])
+def test_pyrochlore_table_equals_oracle(model, L, T):
+    say("GPU case: graph path, pyrochlore table L=%d model=%d T=%g" % (L, model, T))
+    bonds = pyrosw.pyro_sw_bonds(L)
+    g = pyrosw.Graph(bonds, 16 * L ** 3, model, T, seed=50 + L, start=pyrosw.PYRO_START_RANDOM)
+    o = oracle.Oracle(L=L, model=model, T=T, seed=50 + L, start=oracle.RANDOM)
+    np.testing.assert_array_equal(g.spins(), o.spins())
+    compare(g, o, 120, model)
+    g.close()
+
+
+@pytest.mark.parametrize("model,L,T", [(1, 8, 4.511524), (1, 5, 10.0), (2, 6, 2.20182), (3, 5, 1.4430)])
+def test_simple_cubic_equals_oracle(model, L, T):
+    say("GPU case: graph path, simple cubic L=%d model=%d T=%g" % (L, model, T))
+    g = pyrosw.Graph(pyrosw.simple_cubic_bonds(L), L ** 3, model, T, seed=70 + L)
+    o = oracle.Oracle(L=L, model=model, T=T, seed=70 + L, start=oracle.RANDOM, lattice="sc")
+    compare(g, o, 200, model)
+    g.close()
+
+
+@pytest.mark.parametrize("model", [1, 2])
+def test_random_graph_equals_oracle(model):
+    rng = np.random.default_rng(9)
+    N, NB = 600, 1800
+    a = rng.integers(0, N, NB)
+    b = (a + 1 + rng.integers(0, N - 1, NB)) % N  # never a self-loop; repeated pairs allowed
+    T = 2.5 if model == 1 else 1.2
+    say("GPU case: graph path, random graph N=%d NB=%d model=%d" % (N, NB, model))
+    g = pyrosw.Graph((a, b), N, model, T, seed=123)
+    o = oracle.Oracle(model=model, T=T, seed=123, start=oracle.RANDOM, lattice="edges", edges=(a, b), n_sites=N)
+    compare(g, o, 300, model)
+    g.close()
+
+
+def test_graph_without_bonds_and_with_vacancies():
+    say("GPU case: graph path, no bonds; diluted simple cubic")
+    N = 1000
+    g = pyrosw.Graph((np.zeros(0, np.int32), np.zeros(0, np.int32)), N, 1, 3.0, seed=4)
+    o = oracle.Oracle(model=1, T=3.0, seed=4, start=oracle.RANDOM, lattice="edges",
+                      edges=(np.zeros(0, np.int32), np.zeros(0, np.int32)), n_sites=N)
+    compare(g, o, 50, 1)
+    assert np.array_equal(g.labels(), np.arange(N))
+    g.close()
+    L = 7
+    s0 = workloads.diluted_spins(L ** 3, 1, 0.3, 8)
+    g = pyrosw.Graph(pyrosw.simple_cubic_bonds(L), L ** 3, 1, 3.5, seed=8, start=pyrosw.PYRO_START_COLD)
+    o = oracle.Oracle(L=L, model=1, T=3.5, seed=8, start=oracle.COLD, lattice="sc")
+    g.set_spins(s0, 0)
+    o.set_spins(s0, 0)
+    compare(g, o, 100, 1)
+    assert np.all(g.spins()[s0 == 0] == 0)
+    g.close()
+
+
+def test_large_simple_cubic_properties():
+    """L = 128 simple cubic (2,097,152 sites) at its T_c: canonical labels,
+    equal pre-flip spins within a cluster, exact M and bond sum."""
+    L, T, seed = 128, 4.511524, 5
+    N = L ** 3
+    say("GPU case: graph path, simple cubic L=%d" % L)
+    g = pyrosw.Graph(pyrosw.simple_cubic_bonds(L), N, 1, T, seed=seed)
+    g.sweep(5)
+    before = g.spins()
+    g.sweep(1)
+    rec = g.moments()
+    after, lab = g.spins(), g.labels()
+    g.close()
+    assert np.all(lab <= np.arange(N)) and np.array_equal(lab[lab], lab)
+    assert np.array_equal(before[lab], before)
+    s = after.astype(np.int64).reshape(L, L, L)
+    bsum = sum(int((s * np.roll(s, -1, axis=ax)).sum()) for ax in (0, 1, 2))
+    assert int(rec["M_int"][-1]) == int(s.sum())
+    assert int(rec["bond_sum"][-1]) == bsum
