@@ -45,9 +45,11 @@ from . import workloads
 SIZE_FACTOR = 16.0 ** (1.0 / 3.0)  # N^(1/3) = 16^(1/3) L (Sec. 3.1)
 
 
-def linear_size(L):
-    """The linear size used in the scaling variable: N^(1/3) with N = 16 L^3."""
-    return SIZE_FACTOR * np.asarray(L, dtype=np.float64)
+def linear_size(L, lattice="pyro"):
+    """The linear size used in the scaling variable: N^(1/3), with N = 16 L^3
+    for the pyrochlore and N = L^3 for the simple-cubic lattice (Sec. 3.4)."""
+    f = SIZE_FACTOR if lattice == "pyro" else 1.0
+    return f * np.asarray(L, dtype=np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -70,6 +72,7 @@ class Protocol:
     J: float = 1.0
     chunk: int = 1000  # sweeps per group call (records drained in between)
     autotune: bool = True
+    lattice: str = "pyro"  # or "sc": the simple-cubic lattice on the generic graph path
 
     def members(self):
         """(L, T index, run, seed) of every lattice, in a fixed order; seeds
@@ -120,22 +123,40 @@ def run_protocol(p: Protocol, device: str = "cuda:0", log=None) -> RunData:
 
     log = log or (lambda s: None)
     members = p.members()
-    lats = [pyrosw.Lattice(L=L, model=p.model, T=p.temps[ti], J=p.J, seed=s,
-                           start=pyrosw.PYRO_START_RANDOM, device=device)
-            for (L, ti, r, s) in members]
-    data = RunData(protocol=p)
-    series = [([], []) for _ in members]
-    g = pyrosw.Group(lats)
-    try:
+    if p.lattice == "pyro":
+        lats = [pyrosw.Lattice(L=L, model=p.model, T=p.temps[ti], J=p.J, seed=s,
+                               start=pyrosw.PYRO_START_RANDOM, device=device)
+                for (L, ti, r, s) in members]
+        g = pyrosw.Group(lats)
         if p.autotune:
             g.autotune(3)
+        sweep_all = g.sweep
+        sites = lambda L: 16 * L ** 3
+    elif p.lattice == "sc":
+        # one generic-graph handle per lattice, each on its own stream
+        tables = {L: pyrosw.simple_cubic_bonds(L) for L in set(m[0] for m in members)}
+        lats = [pyrosw.Graph(tables[L], L ** 3, p.model, p.temps[ti], J=p.J, seed=s,
+                             start=pyrosw.PYRO_START_RANDOM, device=device, stream=0)
+                for (L, ti, r, s) in members]
+        g = None
+
+        def sweep_all(n):
+            for lt in lats:
+                lt.sweep(n)
+
+        sites = lambda L: L ** 3
+    else:
+        raise ValueError("lattice must be 'pyro' or 'sc'")
+    data = RunData(protocol=p)
+    series = [([], []) for _ in members]
+    try:
         total = p.sweeps_per_member()
         torch.cuda.synchronize(device)
         t0 = time.perf_counter()
         done = 0
         while done < total:
             n = min(p.chunk, total - done)
-            g.sweep(n)
+            sweep_all(n)
             for k, lt in enumerate(lats):
                 rec = lt.moments()
                 keep = rec[rec["sweep"] >= p.discard]  # sweep indices start at 0
@@ -147,10 +168,11 @@ def run_protocol(p: Protocol, device: str = "cuda:0", log=None) -> RunData:
         torch.cuda.synchronize(device)
         data.seconds = time.perf_counter() - t0
     finally:
-        g.close()
+        if g is not None:
+            g.close()
         for lt in lats:
             lt.close()
-    data.spin_updates = float(sum(16 * L ** 3 for (L, _, _, _) in members)) * p.sweeps_per_member()
+    data.spin_updates = float(sum(sites(L) for (L, _, _, _) in members)) * p.sweeps_per_member()
     for k, (L, ti, r, _) in enumerate(members):
         data.m2.setdefault(L, {}).setdefault(ti, {})[r] = np.concatenate(series[k][0])
         data.m4.setdefault(L, {}).setdefault(ti, {})[r] = np.concatenate(series[k][1])
@@ -295,21 +317,23 @@ def collapse_quality(xs, ys, dys):
     return total / count if count else math.inf
 
 
-def _scaled(temps, Ls, tc, nu, values, errs, power=0.0):
-    """Scaling variable t Lp^(1/nu) and values Lp^power per size (sorted)."""
+def _scaled(temps, Ls, tc, nu, values, errs, power=0.0, lattice="pyro", d1=1.0, d2=1.0):
+    """Scaling variable D1 t Lp^(1/nu) and values Lp^power / D2 per size
+    (sorted by the variable); D1 = D2 = 1 unless two lattices are compared
+    (Sec. 3.4)."""
     xs, ys, dys = [], [], []
     T = np.asarray(temps, dtype=np.float64)
     for li, L in enumerate(Ls):
-        lp = float(linear_size(L))
-        x = (T - tc) / tc * lp ** (1.0 / nu)
+        lp = float(linear_size(L, lattice))
+        x = d1 * (T - tc) / tc * lp ** (1.0 / nu)
         o = np.argsort(x)
         xs.append(x[o])
-        ys.append(values[li][o] * lp ** power)
-        dys.append(errs[li][o] * lp ** power)
+        ys.append(values[li][o] * lp ** power / d2)
+        dys.append(errs[li][o] * lp ** power / d2)
     return xs, ys, dys
 
 
-def fit_tc_nu(temps, Ls, U, dU, tc0, nu0):
+def fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice="pyro"):
     """T_c and nu minimising the collapse quality of U (Eq. 3)."""
     from scipy.optimize import minimize
 
@@ -317,7 +341,7 @@ def fit_tc_nu(temps, Ls, U, dU, tc0, nu0):
         tc, nu = v
         if nu <= 0.05:
             return 1e30
-        return collapse_quality(*_scaled(temps, Ls, tc, nu, U, dU))
+        return collapse_quality(*_scaled(temps, Ls, tc, nu, U, dU, lattice=lattice))
 
     best = minimize(cost, x0=[tc0, nu0], method="Nelder-Mead",
                     options=dict(xatol=1e-7, fatol=1e-9, maxiter=4000,
@@ -325,31 +349,31 @@ def fit_tc_nu(temps, Ls, U, dU, tc0, nu0):
     return float(best.x[0]), float(best.x[1]), float(best.fun)
 
 
-def fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lo=0.2, hi=0.9):
+def fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lo=0.2, hi=0.9, lattice="pyro"):
     """beta/nu minimising the collapse quality of <m^2> (N^(1/3))^(2 beta/nu)
     at fixed T_c and nu (Eq. 4)."""
     from scipy.optimize import minimize_scalar
 
     def cost(bn):
-        return collapse_quality(*_scaled(temps, Ls, tc, nu, m2, dm2, power=2.0 * bn))
+        return collapse_quality(*_scaled(temps, Ls, tc, nu, m2, dm2, power=2.0 * bn, lattice=lattice))
 
     best = minimize_scalar(cost, bounds=(lo, hi), method="bounded", options=dict(xatol=1e-6))
     return float(best.x), float(best.fun)
 
 
-def analyse(temps, Ls, rm: np.ndarray, tc0: float, nu0: float):
+def analyse(temps, Ls, rm: np.ndarray, tc0: float, nu0: float, lattice="pyro"):
     """Everything the paper extracts from one model's scan: U and <m^2>
     tables, Binder crossings, T_c, nu, beta/nu (jackknife errors)."""
     U, dU, m2, dm2 = estimates(rm)
-    tc, nu, q = fit_tc_nu(temps, Ls, U, dU, tc0, nu0)
-    bn, qb = fit_beta_nu(temps, Ls, m2, dm2, tc, nu)
+    tc, nu, q = fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice)
+    bn, qb = fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lattice=lattice)
     runs_first = np.moveaxis(rm, 2, 0)
 
     def refit(v):
         sub = np.moveaxis(v, 0, 2)
         u, du, mm, dmm = estimates(sub)
-        t, n, _ = fit_tc_nu(temps, Ls, u, du, tc, nu)
-        b, _ = fit_beta_nu(temps, Ls, mm, dmm, t, n)
+        t, n, _ = fit_tc_nu(temps, Ls, u, du, tc, nu, lattice)
+        b, _ = fit_beta_nu(temps, Ls, mm, dmm, t, n, lattice=lattice)
         return np.array([t, n, b])
 
     R = rm.shape[2]
@@ -366,6 +390,52 @@ def analyse(temps, Ls, rm: np.ndarray, tc0: float, nu0: float):
     )
 
 
+def universal_factors(pyro: dict, sc: dict, nu: float, bn: float):
+    """Nonuniversal metric factors of the pyrochlore lattice against the
+    simple cubic (Sec. 3.4): with D1 = D2 = 1 for the simple cubic, D1
+    minimises the collapse quality of U against D1 t (N^(1/3))^(1/nu) over
+    the sizes of both lattices, then D2 that of <m^2> (N^(1/3))^(2 beta/nu) / D2
+    at that D1.  Each lattice uses its own T_c.  ``pyro`` and ``sc`` hold
+    temps, L, Tc and run_means as written by a scan; errors are the
+    jackknife over runs (run r of both lattices left out together)."""
+    from scipy.optimize import minimize_scalar
+
+    rp, rs = np.asarray(pyro["run_means"]), np.asarray(sc["run_means"])
+
+    def fit(rp, rs):
+        Up, dUp, mp, dmp = estimates(rp)
+        Us, dUs, ms, dms = estimates(rs)
+        sc_u = _scaled(sc["temps"], sc["L"], sc["Tc"], nu, Us, dUs, lattice="sc")
+        sc_m = _scaled(sc["temps"], sc["L"], sc["Tc"], nu, ms, dms, power=2.0 * bn, lattice="sc")
+
+        def cost1(d1):
+            cp = _scaled(pyro["temps"], pyro["L"], pyro["Tc"], nu, Up, dUp, d1=d1)
+            return collapse_quality(*[a + b for a, b in zip(cp, sc_u)])
+
+        d1 = minimize_scalar(cost1, bounds=(0.3, 3.0), method="bounded", options=dict(xatol=1e-6)).x
+
+        def cost2(d2):
+            cp = _scaled(pyro["temps"], pyro["L"], pyro["Tc"], nu, mp, dmp, power=2.0 * bn, d1=d1, d2=d2)
+            return collapse_quality(*[a + b for a, b in zip(cp, sc_m)])
+
+        d2 = minimize_scalar(cost2, bounds=(0.3, 3.0), method="bounded", options=dict(xatol=1e-6)).x
+        return np.array([d1, d2, cost1(d1), cost2(d2)])
+
+    full = fit(rp, rs)
+    R = min(rp.shape[2], rs.shape[2])
+    err = np.full(2, np.nan)
+    if R >= 3:
+        loo = np.array([fit(np.delete(rp, i, axis=2), np.delete(rs, i, axis=2))[:2] for i in range(R)])
+        err = np.sqrt((R - 1) / R * np.sum((loo - loo.mean(axis=0)) ** 2, axis=0))
+    return dict(D1=float(full[0]), dD1=float(err[0]), D2=float(full[1]), dD2=float(err[1]),
+                quality_U=float(full[2]), quality_m2=float(full[3]))
+
+
+# Simple-cubic critical temperatures the paper quotes from the literature
+# (Sec. 3.1-3.3) and its metric factors of the pyrochlore lattice (Sec. 3.4).
+SC_TC = {workloads.ISING: 4.511524, workloads.XY: 2.20182, workloads.HEISENBERG: 1.4430}
+PAPER_D = {workloads.ISING: (1.0, 0.91), workloads.XY: (0.96, 0.91), workloads.HEISENBERG: (0.92, 0.91)}
+
 # Estimates the paper prints (Sec. 3.1-3.3): T_c, nu, beta/nu with the error
 # in the last digits.
 PAPER = {
@@ -378,6 +448,9 @@ PAPER = {
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Finite-size-scaling scan of one model on the GPU")
     ap.add_argument("--model", type=int, default=1, choices=(1, 2, 3))
+    ap.add_argument("--lattice", default="pyro", choices=("pyro", "sc"))
+    ap.add_argument("--universal", nargs=2, metavar=("PYRO_JSON", "SC_JSON"), default=None,
+                    help="no scan: metric factors D1, D2 from two scans' output (Sec. 3.4)")
     ap.add_argument("--L", type=int, nargs="+", default=[32, 48, 64, 96])
     ap.add_argument("--temps", type=float, nargs="*", default=None,
                     help="temperatures (default: 13 over T_c (1 +- w), w from WINDOW)")
@@ -387,15 +460,25 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=1000)
     args = ap.parse_args(argv)
-    temps = tuple(args.temps) if args.temps else default_temperatures(args.model)
+    if args.universal:
+        pyro, sc = (json.loads(open(f).read().strip().splitlines()[-1]) for f in args.universal)
+        ref = PAPER[pyro["model"]]
+        res = universal_factors(pyro, sc, ref["nu"][0], ref["beta_over_nu"][0])
+        res.update(model=pyro["model"], paper_D1_D2=PAPER_D[pyro["model"]])
+        print(json.dumps(res))
+        return
+    tc_ref = PAPER[args.model]["Tc"][0] if args.lattice == "pyro" else SC_TC[args.model]
+    temps = tuple(args.temps) if args.temps else tuple(
+        float(t) for t in tc_ref * (1.0 + np.linspace(-WINDOW[args.model], WINDOW[args.model], 13)))
     p = Protocol(model=args.model, Ls=tuple(args.L), temps=temps, discard=args.discard,
-                 measure=args.measure, runs=args.runs, seed=args.seed, chunk=args.chunk)
+                 measure=args.measure, runs=args.runs, seed=args.seed, chunk=args.chunk, lattice=args.lattice)
     data = run_protocol(p, log=lambda s: print(s, file=sys.stderr, flush=True))
     ref = PAPER[args.model]
-    res = analyse(temps, p.Ls, run_means(data), ref["Tc"][0], ref["nu"][0])
-    res.update(model=args.model, L=list(p.Ls), temps=list(temps), discard=p.discard,
+    rm = run_means(data)
+    res = analyse(temps, p.Ls, rm, tc_ref, ref["nu"][0], args.lattice)
+    res.update(model=args.model, lattice=args.lattice, L=list(p.Ls), temps=list(temps), discard=p.discard,
                measure=p.measure, runs=p.runs, seconds=data.seconds,
-               spin_updates_per_s=data.spin_updates / data.seconds, paper=ref)
+               spin_updates_per_s=data.spin_updates / data.seconds, paper=ref, run_means=rm.tolist())
     print(json.dumps(res))
 
 

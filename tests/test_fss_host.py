@@ -141,3 +141,46 @@ def test_run_averaged_ratio_equals_the_oracle_binder_of_pooled_records():
     U, _, _, _ = fss.estimates(fss.run_means(data))
     want = oracle.binder(np.concatenate(pooled))
     assert U[0, 0] == pytest.approx(want, rel=1e-12)
+
+
+def test_universal_metric_factors_are_recovered():
+    """Two lattices whose data follow the universal forms of Sec. 3.4 with
+    known metric factors (simple cubic D1 = D2 = 1, pyrochlore D1 = 0.96,
+    D2 = 0.91) and their own T_c: the fit returns the pyrochlore factors."""
+    nu, bn = 0.672, 0.515
+    f1 = lambda x: 2.0 + np.tanh(0.3 * x)
+    f2 = lambda x: 0.6 * np.exp(-0.3 * x)
+    rng = np.random.default_rng(12)
+
+    def scan(lattice, Ls, tc, d1, d2, noise=1e-3, runs=5):
+        temps = tuple(float(t) for t in tc * (1 + np.linspace(-1.2e-3, 1.2e-3, 13)))
+        rm = np.zeros((len(Ls), len(temps), runs, 2))
+        T = np.asarray(temps)
+        for li, L in enumerate(Ls):
+            lp = fss.linear_size(L, lattice)
+            x = d1 * (T - tc) / tc * lp ** (1 / nu)
+            m2 = d2 * lp ** (-2 * bn) * f2(x)
+            m4 = f1(x) * m2 ** 2
+            for r in range(runs):
+                rm[li, :, r, 0] = m2 * (1 + noise * rng.normal(size=len(T)))
+                rm[li, :, r, 1] = m4 * (1 + noise * rng.normal(size=len(T)))
+        return dict(temps=temps, L=list(Ls), Tc=tc, run_means=rm.tolist())
+
+    pyro = scan("pyro", (32, 48, 64), 2.0285, 0.96, 0.91)
+    sc = scan("sc", (64, 96, 128), 2.20182, 1.0, 1.0)
+    res = fss.universal_factors(pyro, sc, nu, bn)
+    assert abs(res["D1"] - 0.96) < max(4 * res["dD1"], 0.01)
+    assert abs(res["D2"] - 0.91) < max(4 * res["dD2"], 0.01)
+    assert res["quality_U"] < 5 and res["quality_m2"] < 5
+    # the same data with the factors dropped collapse far worse
+    wrong = dict(pyro)
+    rm = np.asarray(pyro["run_means"]).copy()
+    rm[..., 0] /= 0.91
+    rm[..., 1] /= 0.91 ** 2
+    wrong["run_means"] = rm.tolist()
+    assert fss.universal_factors(wrong, sc, nu, bn)["D2"] == pytest.approx(1.0, abs=0.02)
+
+
+def test_simple_cubic_linear_size():
+    assert fss.linear_size(64, "sc") == 64.0
+    assert fss.linear_size(64) == pytest.approx(64 * 16 ** (1 / 3), rel=1e-15)

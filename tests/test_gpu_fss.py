@@ -60,3 +60,24 @@ def test_small_scan(model):
         # small lattices: corrections to scaling move the crossing by up to
         # about half a percent of T_c
         assert abs(t - tc) < 0.006 * tc, (t, e)
+
+
+def test_simple_cubic_scan_members_follow_their_solo_runs():
+    """The driver's simple-cubic scans (generic graph path, one handle per
+    lattice on its own stream) give each lattice its solo trajectory."""
+    tc = fss.SC_TC[workloads.ISING]
+    temps = tuple(float(t) for t in tc * (1.0 + np.linspace(-0.01, 0.01, 5)))
+    p = fss.Protocol(model=workloads.ISING, Ls=(8, 12), temps=temps, discard=200, measure=1000,
+                     runs=2, seed=91, chunk=600, lattice="sc")
+    say("GPU case: FSS scan, simple cubic L %s, %d temperatures" % (p.Ls, len(temps)))
+    data = fss.run_protocol(p, log=say)
+    L, ti, r, seed = p.members()[len(temps) * p.runs + 3 * p.runs + 1]
+    g = pyrosw.Graph(pyrosw.simple_cubic_bonds(L), L ** 3, workloads.ISING, temps[ti], seed=seed,
+                     start=pyrosw.PYRO_START_RANDOM)
+    g.sweep(p.sweeps_per_member())
+    rec = g.moments()
+    g.close()
+    np.testing.assert_array_equal(data.m2[L][ti][r], rec["m2"][p.discard:])
+    U, _, _, _ = fss.estimates(fss.run_means(data))
+    assert np.all(U > 1.0) and np.all(U < 3.0)
+    assert np.all(U[:, 0] < U[:, -1])
