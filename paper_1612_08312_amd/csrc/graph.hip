@@ -54,8 +54,8 @@ struct GraphDesc {
     int32_t *label;
     float *sigma;  // O(n) projections [N]
     float *axis;   // [4]
-    int64_t *ipart;  // Ising partials: [bond blocks] then [site blocks]
-    double *dpart;   // O(n) partials: [bond blocks] then [3][site blocks]
+    int64_t *ipart;  // Ising partials: [kPartBlocks bond blocks][kPartBlocks site blocks]
+    double *dpart;   // O(n) partials: [kPartBlocks bond blocks][3][kPartBlocks site blocks]
     DevRecord *ring;
     uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
     float x0;
@@ -159,14 +159,22 @@ __global__ __launch_bounds__(kBlock) void k_graph_bonds(GraphDesc g, uint32_t t)
     if (active) graph_unite(g.label, i, j);
 }
 
-__global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t, int64_t site_off)
+// The flip and energy passes run a fixed grid of at most kPartBlocks blocks
+// that stride over their sites or bonds, so the record is a fixed-order sum
+// of at most 2 kPartBlocks partials: ipart / dpart hold the bond partials at
+// [0, kPartBlocks) and the site partials (O(n): per component) after them.
+constexpr int kPartBlocks = 2048;
+
+__host__ __device__ inline int part_grid(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), kPartBlocks); }
+
+__global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t)
 {
     __shared__ int64_t ired[16];
     __shared__ double dred[16];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t m = 0;
     double mv[3] = {0.0, 0.0, 0.0};
-    if (i < g.N) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < g.N; i += stride) {
         const int32_t r = graph_root(g.label, (int32_t)i);
         g.label[i] = r;
         const uint32_t c = coin_of(r, t, g.key);
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t, 
                 v = (int8_t)-v;
                 s[i] = v;
             }
-            m = v;
+            m += v;
         } else {
             float *s = (float *)g.spins;
             const float cf = __fmul_rn(-2.0f, g.sigma[i]);
@@ -187,18 +195,17 @@ __global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t, 
                     v = __fmaf_rn(cf, g.axis[k], v);
                     s[(int64_t)k * g.N + i] = v;
                 }
-                mv[k] = (double)v;
+                mv[k] += (double)v;
             }
         }
     }
-    const int64_t nsb = blocks_for(g.N);
     if (g.n == 1) {
         const int64_t bs = block_sum<int64_t>(m, ired);
-        if (threadIdx.x == 0) g.ipart[site_off + blockIdx.x] = bs;
+        if (threadIdx.x == 0) g.ipart[kPartBlocks + blockIdx.x] = bs;
     } else {
         for (int k = 0; k < 3; ++k) {
             const double bs = block_sum<double>(mv[k], dred);
-            if (threadIdx.x == 0) g.dpart[site_off + k * nsb + blockIdx.x] = bs;
+            if (threadIdx.x == 0) g.dpart[kPartBlocks + k * kPartBlocks + blockIdx.x] = bs;
         }
     }
 }
@@ -207,19 +214,18 @@ __global__ __launch_bounds__(kBlock) void k_graph_energy(GraphDesc g)
 {
     __shared__ int64_t ired[16];
     __shared__ double dred[16];
-    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t b0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g.n == 1) {
+        const int8_t *s = (const int8_t *)g.spins;
         int64_t e = 0;
-        if (b < g.NB) {
-            const int8_t *s = (const int8_t *)g.spins;
-            e = (int64_t)s[g.ba[b]] * (int64_t)s[g.bb[b]];
-        }
+        for (int64_t b = b0; b < g.NB; b += stride) e += (int64_t)s[g.ba[b]] * (int64_t)s[g.bb[b]];
         const int64_t bs = block_sum<int64_t>(e, ired);
         if (threadIdx.x == 0) g.ipart[blockIdx.x] = bs;
     } else {
+        const float *s = (const float *)g.spins;
         double e = 0.0;
-        if (b < g.NB) {
-            const float *s = (const float *)g.spins;
+        for (int64_t b = b0; b < g.NB; b += stride) {
             const int32_t i = g.ba[b], j = g.bb[b];
             for (int k = 0; k < g.n; ++k) e += (double)s[(int64_t)k * g.N + i] * (double)s[(int64_t)k * g.N + j];
         }
@@ -228,19 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_graph_energy(GraphDesc g)
     }
 }
 
-// Partials: bond-block sums at [0, nbb), site-block sums from site_off on.
-__global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t t, int slot, int64_t nbb,
-                                                           int64_t site_off)
+__global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t t, int slot)
 {
     __shared__ int64_t ired[16];
     __shared__ double dred[16];
-    const int64_t nsb = blocks_for(g.N);
+    const int nbp = g.NB > 0 ? part_grid(g.NB) : 0, nsp = part_grid(g.N);
     DevRecord r{};
     r.sweep = t;
     if (g.n == 1) {
         int64_t E = 0, M = 0;
-        for (int64_t k = threadIdx.x; k < nbb; k += kBlock) E += g.ipart[k];
-        for (int64_t k = threadIdx.x; k < nsb; k += kBlock) M += g.ipart[site_off + k];
+        for (int k = threadIdx.x; k < nbp; k += kBlock) E += g.ipart[k];
+        for (int k = threadIdx.x; k < nsp; k += kBlock) M += g.ipart[kPartBlocks + k];
         E = block_sum<int64_t>(E, ired);
         M = block_sum<int64_t>(M, ired);
         if (threadIdx.x == 0) {
@@ -255,9 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t
         }
     } else {
         double S = 0.0, M[3] = {0.0, 0.0, 0.0};
-        for (int64_t k = threadIdx.x; k < nbb; k += kBlock) S += g.dpart[k];
+        for (int k = threadIdx.x; k < nbp; k += kBlock) S += g.dpart[k];
         for (int c = 0; c < 3; ++c)
-            for (int64_t k = threadIdx.x; k < nsb; k += kBlock) M[c] += g.dpart[site_off + c * nsb + k];
+            for (int k = threadIdx.x; k < nsp; k += kBlock) M[c] += g.dpart[kPartBlocks + c * kPartBlocks + k];
         S = block_sum<double>(S, dred);
         for (int c = 0; c < 3; ++c) M[c] = block_sum<double>(M[c], dred);
         if (threadIdx.x == 0) {
@@ -276,13 +280,12 @@ __global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t
 hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStream_t st)
 {
     const int nsb = blocks_for(g.N), nbb = blocks_for(g.NB);
-    const int64_t site_off = std::max(nbb, 1);  // as sized at init
     if (g.n > 1) k_graph_axis<<<1, 64, 0, st>>>(g, t);
     k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
     if (nbb > 0) k_graph_bonds<<<nbb, kBlock, 0, st>>>(g, t);
-    k_graph_flip<<<nsb, kBlock, 0, st>>>(g, t, site_off);
-    if (nbb > 0) k_graph_energy<<<nbb, kBlock, 0, st>>>(g);
-    k_graph_finalize<<<1, kBlock, 0, st>>>(g, t, slot, (int64_t)nbb, site_off);
+    k_graph_flip<<<part_grid(g.N), kBlock, 0, st>>>(g, t);
+    if (nbb > 0) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
+    k_graph_finalize<<<1, kBlock, 0, st>>>(g, t, slot);
     return hipGetLastError();
 }
 
@@ -379,12 +382,11 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     g->NB = n_bonds;
     g->J = J;
     g->seed = seed;
-    const int64_t nsb = blocks_for(n_sites), nbb = std::max<int64_t>(blocks_for(n_bonds), 1);
     const size_t spin_bytes = model == PYRO_ISING ? (size_t)n_sites : sizeof(float) * model * (size_t)n_sites;
     size_t off[9], total = 0;
     const size_t sizes[9] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
                              sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
-                             16, sizeof(int64_t) * (size_t)(nbb + nsb), sizeof(double) * (size_t)(nbb + 3 * nsb),
+                             16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
                              sizeof(DevRecord) * kGraphRing};
     for (int k = 0; k < 9; ++k) {
         off[k] = total;
@@ -423,18 +425,28 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     d.J = J;
     d.key = philox_key(seed);
     graph_params(g, T);
-    *out = g;
+    hipError_t e = hipSuccess;
     if (n_bonds > 0) {
-        GHIP(hipMemcpy((void *)d.ba, bond_a, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice));
-        GHIP(hipMemcpy((void *)d.bb, bond_b, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice));
+        e = hipMemcpy((void *)d.ba, bond_a, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void *)d.bb, bond_b, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
     }
     RepDesc rd{};
     rd.N = n_sites;
     rd.spins = d.spins;
     rd.label = d.label;
     rd.key = d.key;
-    GHIP(launch_init(rd, model, start, g->stream));
-    GHIP(hipStreamSynchronize(g->stream));
+    if (e == hipSuccess) e = launch_init(rd, model, start, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {  // nothing is handed out: release what was taken
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(g->stream);
+        hipFree(g->mem);
+        if (g->own_stream) hipStreamDestroy(g->stream);
+        delete g;
+        return gfail(PYRO_EDEVICE, std::string("graph set-up: ") + hipGetErrorString(e));
+    }
+    *out = g;
     return PYRO_OK;
 }
 
