@@ -335,7 +335,7 @@ int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls
  * site, so the pyrochlore table of pyro_sw_bonds reproduces that sweep's
  * trajectory bit for bit.  No tiles: one thread per bond or site, with the
  * global union-find of the pyrochlore sweep; slower, for any lattice.
- *   pyro_sw_graph_init     n_sites in [1, 2^31 - 1], n_bonds in [0, 2^33];
+ *   pyro_sw_graph_init     n_sites in [1, 2^31 - 1], n_bonds in [0, 2^32 - 1];
  *                          ends in range and distinct (EINVAL otherwise);
  *                          host arrays are copied, the caller keeps them;
  *                          model, T, J, seed, start and stream as in

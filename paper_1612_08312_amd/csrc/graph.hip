@@ -4,12 +4,17 @@
 //
 // No tiles: one thread per bond or per site.  Per sweep:
 //   O(n) only  k_graph_axis       embedding axis of the sweep (one thread)
-//              k_graph_prepare    label[i] = i; O(n): sigma_i = s_i . r
-//              k_graph_bonds      activation of each bond, and union of its two
-//                                 sites in the global forest (index linking:
-//                                 the larger root is hooked under the smaller
-//                                 by compare-and-swap, so every tree root is
-//                                 its cluster's smallest site)
+//   O(n) only  k_graph_prepare    sigma_i = s_i . r
+//              k_graph_local      sites cut into windows of 2048 indices, one
+//                                 workgroup each: activation of the bonds with
+//                                 both ends in the window and their union in
+//                                 LDS; every site stores its local root
+//              k_graph_cross      activation of the bonds between windows and
+//                                 union of their ends in the global forest
+//                                 (index linking: the larger root is hooked
+//                                 under the smaller by compare-and-swap, so
+//                                 every tree root is its cluster's smallest
+//                                 site)
 //              k_graph_flip       root of each site (pointer chase, written
 //                                 back), flip coin of the root, flip or
 //                                 reflection, magnetisation partials
@@ -48,8 +53,12 @@ constexpr int kGraphRing = 1024;  // device records between drains
 
 struct GraphDesc {
     int64_t N, NB;
+    int64_t n_cross;  // bonds between windows (the last n_cross of the bond arrays)
     int n;  // 1 Ising, 2 XY, 3 Heisenberg
-    const int32_t *ba, *bb;
+    const int32_t *ba, *bb;  // bond ends: bonds inside one site window first, grouped by window,
+                             // then the bonds between windows
+    const uint32_t *bond_id; // position of each bond in the caller's table (keys its draws)
+    const int64_t *wstart;   // [nwin + 1] first bond of each window; wstart[nwin] = first bond between windows
     void *spins;  // int8 [N] or float [n][N]
     int32_t *label;
     float *sigma;  // O(n) projections [N]
@@ -122,41 +131,88 @@ __global__ __launch_bounds__(kBlock) void k_graph_prepare(GraphDesc g)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.N) return;
-    g.label[i] = (int32_t)i;
-    if (g.n == 1) return;
     const float *s = (const float *)g.spins;
     const float r[3] = {g.axis[0], g.axis[1], g.axis[2]};
     const float v[3] = {s[i], s[g.N + i], g.n == 3 ? s[2 * g.N + i] : 0.0f};
     g.sigma[i] = g.n == 2 ? project<2>(v, r) : project<3>(v, r);
 }
 
-__global__ __launch_bounds__(kBlock) void k_graph_bonds(GraphDesc g, uint32_t t)
+// Activation of bond b (its position in the caller's table) between sites
+// i and j in sweep t.
+__device__ __forceinline__ bool graph_bond_active(const GraphDesc &g, uint32_t b, int32_t i, int32_t j, uint32_t t)
 {
-    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (b >= g.NB) return;
-    const int32_t i = g.ba[b], j = g.bb[b];
-    bool active;
     if (g.n == 1) {
         const int8_t *s = (const int8_t *)g.spins;
         const int8_t si = s[i], sj = s[j];
-        active = false;
-        if (si == sj && si != 0) {
-            const uint4 w = philox4x32_10((uint32_t)(b >> 4), t, kStreamBond, 0u, g.key);
-            const uint32_t k = (uint32_t)b & 15u;
-            const uint32_t hi = (word_of(w, k >> 2) >> (8 * (k & 3u))) & 0xFFu;
-            if (hi != g.thr_hi) {
-                active = hi < g.thr_hi;
-            } else {
-                const uint4 v = philox4x32_10((uint32_t)(b >> 2), t, kStreamBondLo, 0u, g.key);
-                active = (word_of(v, (uint32_t)b & 3u) & 0xFFFFFFu) < g.thr_lo;
-            }
-        }
-    } else {
-        const float x = __fmul_rn(__fmul_rn(g.x0, g.sigma[i]), g.sigma[j]);
-        const uint4 w = philox4x32_10((uint32_t)(b >> 2), t, kStreamBond, 0u, g.key);
-        active = on_bond_active(x, word_of(w, (uint32_t)b & 3u));
+        if (si != sj || si == 0) return false;
+        const uint4 w = philox4x32_10(b >> 4, t, kStreamBond, 0u, g.key);
+        const uint32_t k = b & 15u;
+        const uint32_t hi = (word_of(w, k >> 2) >> (8 * (k & 3u))) & 0xFFu;
+        if (hi != g.thr_hi) return hi < g.thr_hi;
+        const uint4 v = philox4x32_10(b >> 2, t, kStreamBondLo, 0u, g.key);
+        return (word_of(v, b & 3u) & 0xFFFFFFu) < g.thr_lo;
     }
-    if (active) graph_unite(g.label, i, j);
+    const float x = __fmul_rn(__fmul_rn(g.x0, g.sigma[i]), g.sigma[j]);
+    const uint4 w = philox4x32_10(b >> 2, t, kStreamBond, 0u, g.key);
+    return on_bond_active(x, word_of(w, b & 3u));
+}
+
+// Sites are cut into windows of kWindow consecutive indices; bonds are
+// grouped (at set-up) by the window of their first end.
+constexpr int kWindow = 2048;
+
+__device__ __forceinline__ int lds_root(const int *P, int x)
+{
+    for (;;) {
+        const int p = __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+// One workgroup per window: union of the active bonds with both ends in the
+// window in LDS (index linking with atomic min, so each local root is the
+// smallest site of its local component), then every site of the window
+// stores the global index of its local root.
+__global__ __launch_bounds__(kBlock) void k_graph_local(GraphDesc g, uint32_t t)
+{
+    __shared__ int P[kWindow];
+    const int64_t base = (int64_t)blockIdx.x * kWindow;
+    const int nloc = (int)std::min<int64_t>(kWindow, g.N - base);
+    for (int k = threadIdx.x; k < nloc; k += kBlock) P[k] = k;
+    __syncthreads();
+    const int64_t b1 = g.wstart[blockIdx.x + 1];
+    for (int64_t q = g.wstart[blockIdx.x] + threadIdx.x; q < b1; q += kBlock) {
+        const int32_t i = g.ba[q], j = g.bb[q];
+        if (j < base || j >= base + nloc) continue;  // crosses windows: the cross pass
+        if (!graph_bond_active(g, g.bond_id[q], i, j, t)) continue;
+        int a = (int)(i - base), b = (int)(j - base);
+        for (;;) {
+            a = lds_root(P, a);
+            b = lds_root(P, b);
+            if (a == b) break;
+            if (a < b) {
+                const int x = a;
+                a = b;
+                b = x;
+            }
+            const int old = __hip_atomic_fetch_min(P + a, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == a) break;
+            a = old;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nloc; k += kBlock) g.label[base + k] = (int32_t)(base + lds_root(P, k));
+}
+
+// Bonds whose ends lie in different windows: union in the global forest of
+// local roots (after every window has stored its labels).
+__global__ __launch_bounds__(kBlock) void k_graph_cross(GraphDesc g, uint32_t t)
+{
+    const int64_t q = g.wstart[(g.N + kWindow - 1) / kWindow] + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= g.NB) return;
+    const int32_t i = g.ba[q], j = g.bb[q];
+    if (graph_bond_active(g, g.bond_id[q], i, j, t)) graph_unite(g.label, i, j);
 }
 
 // The flip and energy passes run a fixed grid of at most kPartBlocks blocks
@@ -280,9 +336,12 @@ __global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t
 hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStream_t st)
 {
     const int nsb = blocks_for(g.N), nbb = blocks_for(g.NB);
-    if (g.n > 1) k_graph_axis<<<1, 64, 0, st>>>(g, t);
-    k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
-    if (nbb > 0) k_graph_bonds<<<nbb, kBlock, 0, st>>>(g, t);
+    if (g.n > 1) {
+        k_graph_axis<<<1, 64, 0, st>>>(g, t);
+        k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
+    }
+    k_graph_local<<<blocks_for(g.N, kWindow), kBlock, 0, st>>>(g, t);
+    if (g.n_cross > 0) k_graph_cross<<<blocks_for(g.n_cross), kBlock, 0, st>>>(g, t);
     k_graph_flip<<<part_grid(g.N), kBlock, 0, st>>>(g, t);
     if (nbb > 0) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
     k_graph_finalize<<<1, kBlock, 0, st>>>(g, t, slot);
@@ -365,7 +424,7 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     if (!out) return gfail(PYRO_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_sites < 1 || n_sites > (int64_t)INT32_MAX) return gfail(PYRO_EINVAL, "n_sites must be in [1, 2^31 - 1]");
-    if (n_bonds < 0 || n_bonds > ((int64_t)1 << 33)) return gfail(PYRO_EINVAL, "n_bonds must be in [0, 2^33]");
+    if (n_bonds < 0 || n_bonds > (int64_t)UINT32_MAX) return gfail(PYRO_EINVAL, "n_bonds must be in [0, 2^32 - 1]");
     if (n_bonds > 0 && (!bond_a || !bond_b)) return gfail(PYRO_EINVAL, "bond lists are NULL");
     if (model < PYRO_ISING || model > PYRO_HEISENBERG) return gfail(PYRO_EINVAL, "model must be 1, 2 or 3");
     if (!(T > 0.0)) return gfail(PYRO_EINVAL, "T must be > 0 (inf allowed)");
@@ -383,12 +442,34 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     g->J = J;
     g->seed = seed;
     const size_t spin_bytes = model == PYRO_ISING ? (size_t)n_sites : sizeof(float) * model * (size_t)n_sites;
-    size_t off[9], total = 0;
-    const size_t sizes[9] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
-                             sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
-                             16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
-                             sizeof(DevRecord) * kGraphRing};
-    for (int k = 0; k < 9; ++k) {
+    // Bonds inside one window first, grouped by window (stable counting
+    // sort), then the bonds between windows in table order; bond_id keeps
+    // each one's position in the caller's table.
+    const int64_t nwin = (n_sites + kWindow - 1) / kWindow;
+    std::vector<int64_t> wstart((size_t)nwin + 1, 0);
+    std::vector<int32_t> ga((size_t)n_bonds), gb((size_t)n_bonds);
+    std::vector<uint32_t> gid((size_t)n_bonds);
+    auto inside = [&](int64_t k) { return bond_a[k] / kWindow == bond_b[k] / kWindow; };
+    for (int64_t k = 0; k < n_bonds; ++k)
+        if (inside(k)) ++wstart[(size_t)(bond_a[k] / kWindow) + 1];
+    for (int64_t w = 0; w < nwin; ++w) wstart[(size_t)w + 1] += wstart[(size_t)w];
+    {
+        std::vector<int64_t> cur(wstart.begin(), wstart.end() - 1);
+        int64_t cross = wstart[(size_t)nwin];
+        for (int64_t k = 0; k < n_bonds; ++k) {
+            const int64_t q = inside(k) ? cur[(size_t)(bond_a[k] / kWindow)]++ : cross++;
+            ga[(size_t)q] = bond_a[k];
+            gb[(size_t)q] = bond_b[k];
+            gid[(size_t)q] = (uint32_t)k;
+        }
+    }
+    size_t off[11], total = 0;
+    const size_t sizes[11] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
+                              sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
+                              16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
+                              sizeof(DevRecord) * kGraphRing, sizeof(uint32_t) * (size_t)n_bonds,
+                              sizeof(int64_t) * (size_t)(nwin + 1)};
+    for (int k = 0; k < 11; ++k) {
         off[k] = total;
         total += align256(sizes[k]);
     }
@@ -412,6 +493,7 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     GraphDesc &d = g->d;
     d.N = n_sites;
     d.NB = n_bonds;
+    d.n_cross = n_bonds - wstart[(size_t)nwin];
     d.n = model;
     d.ba = (const int32_t *)(g->mem + off[0]);
     d.bb = (const int32_t *)(g->mem + off[1]);
@@ -422,14 +504,19 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     d.ipart = (int64_t *)(g->mem + off[6]);
     d.dpart = (double *)(g->mem + off[7]);
     d.ring = (DevRecord *)(g->mem + off[8]);
+    d.bond_id = (const uint32_t *)(g->mem + off[9]);
+    d.wstart = (const int64_t *)(g->mem + off[10]);
     d.J = J;
     d.key = philox_key(seed);
     graph_params(g, T);
-    hipError_t e = hipSuccess;
+    hipError_t e = hipMemcpy((void *)d.wstart, wstart.data(), sizeof(int64_t) * wstart.size(), hipMemcpyHostToDevice);
     if (n_bonds > 0) {
-        e = hipMemcpy((void *)d.ba, bond_a, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy((void *)d.bb, bond_b, sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
+            e = hipMemcpy((void *)d.ba, ga.data(), sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void *)d.bb, gb.data(), sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void *)d.bond_id, gid.data(), sizeof(uint32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
     }
     RepDesc rd{};
     rd.N = n_sites;
