@@ -159,7 +159,8 @@ __device__ __forceinline__ bool graph_bond_active(const GraphDesc &g, uint32_t b
 
 // Sites are cut into windows of kWindow consecutive indices; bonds are
 // grouped (at set-up) by the window of their first end.
-constexpr int kWindow = 2048;
+constexpr int kWindow = 4096;
+constexpr int kLocalThreads = 512;  // threads of the window pass
 
 __device__ __forceinline__ int lds_root(const int *P, int x)
 {
@@ -174,15 +175,15 @@ __device__ __forceinline__ int lds_root(const int *P, int x)
 // window in LDS (index linking with atomic min, so each local root is the
 // smallest site of its local component), then every site of the window
 // stores the global index of its local root.
-__global__ __launch_bounds__(kBlock) void k_graph_local(GraphDesc g, uint32_t t)
+__global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint32_t t)
 {
     __shared__ int P[kWindow];
     const int64_t base = (int64_t)blockIdx.x * kWindow;
     const int nloc = (int)std::min<int64_t>(kWindow, g.N - base);
-    for (int k = threadIdx.x; k < nloc; k += kBlock) P[k] = k;
+    for (int k = threadIdx.x; k < nloc; k += kLocalThreads) P[k] = k;
     __syncthreads();
     const int64_t b1 = g.wstart[blockIdx.x + 1];
-    for (int64_t q = g.wstart[blockIdx.x] + threadIdx.x; q < b1; q += kBlock) {
+    for (int64_t q = g.wstart[blockIdx.x] + threadIdx.x; q < b1; q += kLocalThreads) {
         const int32_t i = g.ba[q], j = g.bb[q];
         if (j < base || j >= base + nloc) continue;  // crosses windows: the cross pass
         if (!graph_bond_active(g, g.bond_id[q], i, j, t)) continue;
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_graph_local(GraphDesc g, uint32_t t)
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nloc; k += kBlock) g.label[base + k] = (int32_t)(base + lds_root(P, k));
+    for (int k = threadIdx.x; k < nloc; k += kLocalThreads) g.label[base + k] = (int32_t)(base + lds_root(P, k));
 }
 
 // Bonds whose ends lie in different windows: union in the global forest of
@@ -340,7 +341,7 @@ hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStrea
         k_graph_axis<<<1, 64, 0, st>>>(g, t);
         k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
     }
-    k_graph_local<<<blocks_for(g.N, kWindow), kBlock, 0, st>>>(g, t);
+    k_graph_local<<<blocks_for(g.N, kWindow), kLocalThreads, 0, st>>>(g, t);
     if (g.n_cross > 0) k_graph_cross<<<blocks_for(g.n_cross), kBlock, 0, st>>>(g, t);
     k_graph_flip<<<part_grid(g.N), kBlock, 0, st>>>(g, t);
     if (nbb > 0) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
