@@ -58,14 +58,33 @@ def test_simple_cubic_equals_oracle(model, L, T):
     g.close()
 
 
-@pytest.mark.parametrize("model", [1, 2])
-def test_random_graph_equals_oracle(model):
+@pytest.mark.parametrize("model,L,T", [(1, 24, 4.511524), (2, 17, 2.20182)])
+def test_simple_cubic_across_windows_equals_oracle(model, L, T):
+    """Lattices of several 4096-site windows: bonds inside a window are
+    united in LDS, the others in the global forest."""
+    say("GPU case: graph path, simple cubic across windows L=%d model=%d" % (L, model))
+    g = pyrosw.Graph(pyrosw.simple_cubic_bonds(L), L ** 3, model, T, seed=30 + L)
+    o = oracle.Oracle(L=L, model=model, T=T, seed=30 + L, start=oracle.RANDOM, lattice="sc")
+    compare(g, o, 60, model)
+    g.close()
+
+
+def test_pyrochlore_table_across_windows_equals_oracle():
+    L, T = 7, 4.2139  # 5488 sites: two windows
+    say("GPU case: graph path, pyrochlore table across windows L=%d" % L)
+    g = pyrosw.Graph(pyrosw.pyro_sw_bonds(L), 16 * L ** 3, 1, T, seed=77)
+    o = oracle.Oracle(L=L, model=1, T=T, seed=77, start=oracle.RANDOM)
+    compare(g, o, 60, 1)
+    g.close()
+
+
+@pytest.mark.parametrize("model,N,NB", [(1, 600, 1800), (2, 600, 1800), (1, 20000, 60000), (3, 20000, 60000)])
+def test_random_graph_equals_oracle(model, N, NB):
     rng = np.random.default_rng(9)
-    N, NB = 600, 1800
     a = rng.integers(0, N, NB)
     b = (a + 1 + rng.integers(0, N - 1, NB)) % N  # never a self-loop; repeated pairs allowed
     T = 2.5 if model == 1 else 1.2
-    say("GPU case: graph path, random graph N=%d NB=%d model=%d" % (N, NB, model))
+    say("GPU case: graph path, random graph N=%d NB=%d model=%d" % (N, NB, model))  # N = 20000: five windows
     g = pyrosw.Graph((a, b), N, model, T, seed=123)
     o = oracle.Oracle(model=model, T=T, seed=123, start=oracle.RANDOM, lattice="edges", edges=(a, b), n_sites=N)
     compare(g, o, 300, model)
