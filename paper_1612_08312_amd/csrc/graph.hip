@@ -2,10 +2,11 @@
 // table): the paper's remark that the algorithm carries over to other
 // lattices once a nearest-neighbour table is supplied (Sec. 2, Sec. 4).
 //
-// No tiles: one thread per bond or per site.  Per sweep:
+// No lattice tiles: windows of consecutive site indices, and one thread per
+// bond or per site.  Per sweep:
 //   O(n) only  k_graph_axis       embedding axis of the sweep (one thread)
 //   O(n) only  k_graph_prepare    sigma_i = s_i . r
-//              k_graph_local      sites cut into windows of 2048 indices, one
+//              k_graph_local      sites cut into windows of 4096 indices, one
 //                                 workgroup each: activation of the bonds with
 //                                 both ends in the window and their union in
 //                                 LDS; every site stores its local root
