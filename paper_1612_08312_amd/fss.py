@@ -25,9 +25,11 @@ Readings where the paper leaves the choice open:
     through U_L1(T) - U_L2(T) over the scanned temperatures;
   * the collapse is scored by the quality measure of Houdayer and Hartmann
     (Phys. Rev. B 70, 014418 (2004)): each point is compared with the
-    linear interpolation of every other size at the same scaling variable,
-    in units of the combined error, and the mean of the squared deviations
-    is minimised over the scaling parameters.
+    interpolation of every other size at the same scaling variable, in
+    units of the combined error, and the mean of the squared deviations is
+    minimised over the scaling parameters; the interpolation is quadratic
+    (three nearest points) rather than their linear one, whose curvature
+    bias pulled beta/nu low on synthetic data.
 """
 from __future__ import annotations
 
@@ -291,27 +293,49 @@ def crossings(temps, rm: np.ndarray, Ls):
 # Data collapse
 
 
-def collapse_quality(xs, ys, dys):
+# Interpolation order of the collapse measure: 2 (three-point Lagrange)
+# unless a caller asks for Houdayer and Hartmann's linear interpolation (1).
+COLLAPSE_ORDER = 2
+
+
+def collapse_quality(xs, ys, dys, order=None):
     """Houdayer-Hartmann quality of a collapse: xs, ys, dys are lists (one
     entry per size) of arrays sorted by x.  For every point and every other
     size whose x range brackets it, the other size's value and error are
-    linearly interpolated at that x; the result is the mean of
-    (y - Y)^2 / (dy^2 + dY^2) over all such comparisons (inf if none)."""
+    interpolated at that x (order 1: linearly between the two bracketing
+    points, as Houdayer and Hartmann do; order 2: through the three nearest
+    points, which removes the curvature bias of the linear form on coarse
+    grids); the result is the mean of (y - Y)^2 / (dy^2 + dY^2) over all such
+    comparisons (inf if none)."""
+    order = COLLAPSE_ORDER if order is None else order
     total, count = 0.0, 0
     for i in range(len(xs)):
         for j in range(len(xs)):
             if i == j:
                 continue
             xj, yj, dyj = xs[j], ys[j], dys[j]
+            n = len(xj)
             for x, y, dy in zip(xs[i], ys[i], dys[i]):
                 if x < xj[0] or x > xj[-1]:
                     continue
-                k = int(np.searchsorted(xj, x, side="right")) - 1
-                k = min(max(k, 0), len(xj) - 2)
-                h = xj[k + 1] - xj[k]
-                f = 0.0 if h == 0 else (x - xj[k]) / h
-                Y = (1 - f) * yj[k] + f * yj[k + 1]
-                dY2 = ((1 - f) * dyj[k]) ** 2 + (f * dyj[k + 1]) ** 2
+                if order == 2 and n >= 3:
+                    m = int(np.argmin(np.abs(xj - x)))
+                    m = min(max(m, 1), n - 2)
+                    p = xj[m - 1:m + 2]
+                    if p[0] == p[1] or p[1] == p[2]:
+                        continue
+                    w = np.array([(x - p[1]) * (x - p[2]) / ((p[0] - p[1]) * (p[0] - p[2])),
+                                  (x - p[0]) * (x - p[2]) / ((p[1] - p[0]) * (p[1] - p[2])),
+                                  (x - p[0]) * (x - p[1]) / ((p[2] - p[0]) * (p[2] - p[1]))])
+                    Y = float(w @ yj[m - 1:m + 2])
+                    dY2 = float((w * w) @ (dyj[m - 1:m + 2] ** 2))
+                else:
+                    k = int(np.searchsorted(xj, x, side="right")) - 1
+                    k = min(max(k, 0), n - 2)
+                    h = xj[k + 1] - xj[k]
+                    f = 0.0 if h == 0 else (x - xj[k]) / h
+                    Y = (1 - f) * yj[k] + f * yj[k + 1]
+                    dY2 = ((1 - f) * dyj[k]) ** 2 + (f * dyj[k + 1]) ** 2
                 total += (y - Y) ** 2 / (dy ** 2 + dY2)
                 count += 1
     return total / count if count else math.inf
