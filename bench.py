@@ -53,7 +53,7 @@ def bytes_per_site(shape):
 # each scaled by the same counter's reading for the probe's 256 MiB copy.
 # Valid only for the kernel sources they were taken with (fingerprint).
 MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
-    "local": ("9f403bf519537cc1", 216838949),  # profiles/k_local_ising_L128_traffic.md
+    "local": ("afecf69c860deccf", 216837979),  # profiles/k_local_ising_L128_traffic.md
 }
 
 
