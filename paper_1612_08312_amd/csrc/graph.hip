@@ -67,6 +67,8 @@ struct GraphDesc {
     int64_t *ipart;  // Ising partials: [kPartBlocks bond blocks][kPartBlocks site blocks]
     double *dpart;   // O(n) partials: [kPartBlocks bond blocks][3][kPartBlocks site blocks]
     DevRecord *ring;
+    unsigned long long *eacc;  // Ising: bond sum of the state entering the sweep, summed by the union
+                               // passes; the finalize moves it into the record and clears it
     uint32_t thr_hi, thr_lo;  // Ising threshold split at bit 24
     float x0;
     double J;
@@ -140,22 +142,41 @@ __global__ __launch_bounds__(kBlock) void k_graph_prepare(GraphDesc g)
 
 // Activation of bond b (its position in the caller's table) between sites
 // i and j in sweep t.
-__device__ __forceinline__ bool graph_bond_active(const GraphDesc &g, uint32_t b, int32_t i, int32_t j, uint32_t t)
+__device__ __forceinline__ bool ising_bond_active(const GraphDesc &g, uint32_t b, int8_t si, int8_t sj, uint32_t t)
+{
+    if (si != sj || si == 0) return false;
+    const uint4 w = philox4x32_10(b >> 4, t, kStreamBond, 0u, g.key);
+    const uint32_t k = b & 15u;
+    const uint32_t hi = (word_of(w, k >> 2) >> (8 * (k & 3u))) & 0xFFu;
+    if (hi != g.thr_hi) return hi < g.thr_hi;
+    const uint4 v = philox4x32_10(b >> 2, t, kStreamBondLo, 0u, g.key);
+    return (word_of(v, b & 3u) & 0xFFFFFFu) < g.thr_lo;
+}
+
+// Activation of bond b between sites i and j; for Ising, *e gains s_i s_j of
+// the state entering the sweep (the energy of the previous record).
+__device__ __forceinline__ bool graph_bond_active(const GraphDesc &g, uint32_t b, int32_t i, int32_t j, uint32_t t,
+                                                  int64_t *e)
 {
     if (g.n == 1) {
         const int8_t *s = (const int8_t *)g.spins;
         const int8_t si = s[i], sj = s[j];
-        if (si != sj || si == 0) return false;
-        const uint4 w = philox4x32_10(b >> 4, t, kStreamBond, 0u, g.key);
-        const uint32_t k = b & 15u;
-        const uint32_t hi = (word_of(w, k >> 2) >> (8 * (k & 3u))) & 0xFFu;
-        if (hi != g.thr_hi) return hi < g.thr_hi;
-        const uint4 v = philox4x32_10(b >> 2, t, kStreamBondLo, 0u, g.key);
-        return (word_of(v, b & 3u) & 0xFFFFFFu) < g.thr_lo;
+        *e += (int64_t)si * (int64_t)sj;
+        return ising_bond_active(g, b, si, sj, t);
     }
     const float x = __fmul_rn(__fmul_rn(g.x0, g.sigma[i]), g.sigma[j]);
     const uint4 w = philox4x32_10(b >> 2, t, kStreamBond, 0u, g.key);
     return on_bond_active(x, word_of(w, b & 3u));
+}
+
+// Ising: add a block's bond sum to the sweep's accumulator (integer, so the
+// order of the additions does not matter).
+__device__ __forceinline__ void add_bond_sum(const GraphDesc &g, int64_t e, int64_t *red)
+{
+    if (g.n != 1) return;
+    const int64_t bs = block_sum<int64_t>(e, red);
+    if (threadIdx.x == 0 && bs != 0)
+        __hip_atomic_fetch_add(g.eacc, (unsigned long long)bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sites are cut into windows of kWindow consecutive indices; bonds are
@@ -179,15 +200,17 @@ __device__ __forceinline__ int lds_root(const int *P, int x)
 __global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint32_t t)
 {
     __shared__ int P[kWindow];
+    __shared__ int64_t red[16];
     const int64_t base = (int64_t)blockIdx.x * kWindow;
     const int nloc = (int)std::min<int64_t>(kWindow, g.N - base);
     for (int k = threadIdx.x; k < nloc; k += kLocalThreads) P[k] = k;
     __syncthreads();
     const int64_t b1 = g.wstart[blockIdx.x + 1];
+    int64_t e = 0;
     for (int64_t q = g.wstart[blockIdx.x] + threadIdx.x; q < b1; q += kLocalThreads) {
         const int32_t i = g.ba[q], j = g.bb[q];
-        if (j < base || j >= base + nloc) continue;  // crosses windows: the cross pass
-        if (!graph_bond_active(g, g.bond_id[q], i, j, t)) continue;
+        if (j < base || j >= base + nloc) continue;  // never: set-up puts such bonds in the cross list
+        if (!graph_bond_active(g, g.bond_id[q], i, j, t, &e)) continue;
         int a = (int)(i - base), b = (int)(j - base);
         for (;;) {
             a = lds_root(P, a);
@@ -205,16 +228,22 @@ __global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nloc; k += kLocalThreads) g.label[base + k] = (int32_t)(base + lds_root(P, k));
+    add_bond_sum(g, e, red);
 }
 
 // Bonds whose ends lie in different windows: union in the global forest of
 // local roots (after every window has stored its labels).
 __global__ __launch_bounds__(kBlock) void k_graph_cross(GraphDesc g, uint32_t t)
 {
-    const int64_t q = g.wstart[(g.N + kWindow - 1) / kWindow] + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= g.NB) return;
-    const int32_t i = g.ba[q], j = g.bb[q];
-    if (graph_bond_active(g, g.bond_id[q], i, j, t)) graph_unite(g.label, i, j);
+    __shared__ int64_t red[16];
+    const int64_t first = g.wstart[(g.N + kWindow - 1) / kWindow];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t e = 0;
+    for (int64_t q = first + (int64_t)blockIdx.x * kBlock + threadIdx.x; q < g.NB; q += stride) {
+        const int32_t i = g.ba[q], j = g.bb[q];
+        if (graph_bond_active(g, g.bond_id[q], i, j, t, &e)) graph_unite(g.label, i, j);
+    }
+    add_bond_sum(g, e, red);
 }
 
 // The flip and energy passes run a fixed grid of at most kPartBlocks blocks
@@ -300,15 +329,17 @@ __global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t
     DevRecord r{};
     r.sweep = t;
     if (g.n == 1) {
-        int64_t E = 0, M = 0;
-        for (int k = threadIdx.x; k < nbp; k += kBlock) E += g.ipart[k];
+        // The bond sum of this record's state is counted by the next sweep's
+        // union passes (or by the tail pass at a drain); the host moves it
+        // in.  `reserved` carries the bond sum of the state entering this
+        // sweep, which belongs to the previous record.
+        int64_t M = 0;
         for (int k = threadIdx.x; k < nsp; k += kBlock) M += g.ipart[kPartBlocks + k];
-        E = block_sum<int64_t>(E, ired);
         M = block_sum<int64_t>(M, ired);
         if (threadIdx.x == 0) {
-            r.bond_sum = E;
+            r.reserved = (int64_t)*g.eacc;
+            *g.eacc = 0ull;
             r.M_int = M;
-            r.E = -g.J * (double)E;
             r.M[0] = (double)M;
             const double mm = (double)M / (double)g.N;
             r.m2 = mm * mm;
@@ -335,6 +366,25 @@ __global__ __launch_bounds__(kBlock) void k_graph_finalize(GraphDesc g, uint32_t
     }
 }
 
+// Ising: bond sum of the current state into ring[kGraphRing].bond_sum (the
+// energy of the last record, read at a drain).
+__global__ __launch_bounds__(kBlock) void k_graph_bond_total(GraphDesc g)
+{
+    __shared__ int64_t ired[16];
+    const int nbp = g.NB > 0 ? part_grid(g.NB) : 0;
+    int64_t E = 0;
+    for (int k = threadIdx.x; k < nbp; k += kBlock) E += g.ipart[k];
+    E = block_sum<int64_t>(E, ired);
+    if (threadIdx.x == 0) g.ring[kGraphRing].bond_sum = E;
+}
+
+hipError_t launch_graph_bond_total(const GraphDesc &g, hipStream_t st)
+{
+    if (g.NB > 0) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
+    k_graph_bond_total<<<1, kBlock, 0, st>>>(g);
+    return hipGetLastError();
+}
+
 hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStream_t st)
 {
     const int nsb = blocks_for(g.N), nbb = blocks_for(g.NB);
@@ -343,9 +393,9 @@ hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStrea
         k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
     }
     k_graph_local<<<blocks_for(g.N, kWindow), kLocalThreads, 0, st>>>(g, t);
-    if (g.n_cross > 0) k_graph_cross<<<blocks_for(g.n_cross), kBlock, 0, st>>>(g, t);
+    if (g.n_cross > 0) k_graph_cross<<<part_grid(g.n_cross), kBlock, 0, st>>>(g, t);
     k_graph_flip<<<part_grid(g.N), kBlock, 0, st>>>(g, t);
-    if (nbb > 0) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
+    if (nbb > 0 && g.n > 1) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
     k_graph_finalize<<<1, kBlock, 0, st>>>(g, t, slot);
     return hipGetLastError();
 }
@@ -409,6 +459,20 @@ int graph_drain(pyro_sw_graph *g)
     std::vector<pyro_sw_record> tmp((size_t)g->ring_used);
     GHIP(hipStreamSynchronize(g->stream));
     GHIP(hipMemcpy(tmp.data(), g->d.ring, sizeof(DevRecord) * tmp.size(), hipMemcpyDeviceToHost));
+    if (g->model == PYRO_ISING) {
+        // Record k's bond sum was counted by sweep k + 1 (its `reserved`);
+        // the last one is counted now, from the current state.
+        int64_t tail = 0;
+        GHIP(launch_graph_bond_total(g->d, g->stream));
+        GHIP(hipStreamSynchronize(g->stream));
+        GHIP(hipMemcpy(&tail, &g->d.ring[kGraphRing].bond_sum, sizeof(int64_t), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < tmp.size(); ++k) {
+            const int64_t b = k + 1 < tmp.size() ? tmp[k + 1].reserved : tail;
+            tmp[k].bond_sum = b;
+            tmp[k].E = -g->J * (double)b;
+        }
+        for (auto &r : tmp) r.reserved = 0;
+    }
     for (const auto &r : tmp) g->host_q.push_back(r);
     g->ring_used = 0;
     return PYRO_OK;
@@ -465,13 +529,13 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
             gid[(size_t)q] = (uint32_t)k;
         }
     }
-    size_t off[11], total = 0;
-    const size_t sizes[11] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
+    size_t off[12], total = 0;
+    const size_t sizes[12] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
                               sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
                               16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
-                              sizeof(DevRecord) * kGraphRing, sizeof(uint32_t) * (size_t)n_bonds,
-                              sizeof(int64_t) * (size_t)(nwin + 1)};
-    for (int k = 0; k < 11; ++k) {
+                              sizeof(DevRecord) * (kGraphRing + 1), sizeof(uint32_t) * (size_t)n_bonds,
+                              sizeof(int64_t) * (size_t)(nwin + 1), sizeof(unsigned long long)};
+    for (int k = 0; k < 12; ++k) {
         off[k] = total;
         total += align256(sizes[k]);
     }
@@ -508,10 +572,12 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     d.ring = (DevRecord *)(g->mem + off[8]);
     d.bond_id = (const uint32_t *)(g->mem + off[9]);
     d.wstart = (const int64_t *)(g->mem + off[10]);
+    d.eacc = (unsigned long long *)(g->mem + off[11]);
     d.J = J;
     d.key = philox_key(seed);
     graph_params(g, T);
     hipError_t e = hipMemcpy((void *)d.wstart, wstart.data(), sizeof(int64_t) * wstart.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d.eacc, 0, sizeof(unsigned long long));
     if (n_bonds > 0) {
         if (e == hipSuccess)
             e = hipMemcpy((void *)d.ba, ga.data(), sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
