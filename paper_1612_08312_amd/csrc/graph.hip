@@ -200,17 +200,33 @@ __device__ __forceinline__ int lds_root(const int *P, int x)
 __global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint32_t t)
 {
     __shared__ int P[kWindow];
+    __shared__ float SG[kWindow];  // the window's spins (Ising, as float) or projections (O(n))
     __shared__ int64_t red[16];
     const int64_t base = (int64_t)blockIdx.x * kWindow;
     const int nloc = (int)std::min<int64_t>(kWindow, g.N - base);
-    for (int k = threadIdx.x; k < nloc; k += kLocalThreads) P[k] = k;
+    for (int k = threadIdx.x; k < nloc; k += kLocalThreads) {
+        P[k] = k;
+        SG[k] = g.n == 1 ? (float)((const int8_t *)g.spins)[base + k] : g.sigma[base + k];
+    }
     __syncthreads();
     const int64_t b1 = g.wstart[blockIdx.x + 1];
     int64_t e = 0;
     for (int64_t q = g.wstart[blockIdx.x] + threadIdx.x; q < b1; q += kLocalThreads) {
         const int32_t i = g.ba[q], j = g.bb[q];
         if (j < base || j >= base + nloc) continue;  // never: set-up puts such bonds in the cross list
-        if (!graph_bond_active(g, g.bond_id[q], i, j, t, &e)) continue;
+        const float vi = SG[i - base], vj = SG[j - base];
+        const uint32_t bid = g.bond_id[q];
+        bool active;
+        if (g.n == 1) {
+            const int8_t si = (int8_t)vi, sj = (int8_t)vj;
+            e += (int64_t)si * (int64_t)sj;
+            active = ising_bond_active(g, bid, si, sj, t);
+        } else {
+            const float x = __fmul_rn(__fmul_rn(g.x0, vi), vj);
+            const uint4 w = philox4x32_10(bid >> 2, t, kStreamBond, 0u, g.key);
+            active = on_bond_active(x, word_of(w, bid & 3u));
+        }
+        if (!active) continue;
         int a = (int)(i - base), b = (int)(j - base);
         for (;;) {
             a = lds_root(P, a);
