@@ -341,18 +341,20 @@ def diluted_throughput(sweeps, stream, dev):
 
 def graph_throughput(sweeps, stream, dev):
     """The generic graph path (any bond table): simple-cubic Ising L = 256 at
-    its T_c, and the pyrochlore L = 128 table at T = 4.2139 for comparison
-    with the tiled sweep; spin-updates/s after 10 warm-up sweeps."""
+    its T_c, the pyrochlore L = 128 table at T = 4.2139 for comparison with
+    the tiled sweep, and XY on the simple-cubic L = 128 table at its T_c;
+    spin-updates/s after 10 warm-up sweeps."""
     import torch
 
     from paper_1612_08312_amd import pyrosw, workloads
 
     sc = workloads.SC_ISING_L256
-    cases = (("simple_cubic_L256", pyrosw.simple_cubic_bonds(sc["L"]), sc["L"] ** 3, sc["T"], sc["seed"]),
-             ("pyrochlore_L128", pyrosw.pyro_sw_bonds(128), 16 * 128 ** 3, 4.2139, 3))
+    cases = (("simple_cubic_L256", pyrosw.simple_cubic_bonds(sc["L"]), sc["L"] ** 3, 1, sc["T"], sc["seed"]),
+             ("pyrochlore_L128", pyrosw.pyro_sw_bonds(128), 16 * 128 ** 3, 1, 4.2139, 3),
+             ("xy_simple_cubic_L128", pyrosw.simple_cubic_bonds(128), 128 ** 3, 2, 2.20182, 4))
     out = {}
-    for name, bonds, n, T, seed in cases:
-        g = pyrosw.Graph(bonds, n, 1, T, seed=seed, device=dev, stream=stream)
+    for name, bonds, n, model, T, seed in cases:
+        g = pyrosw.Graph(bonds, n, model, T, seed=seed, device=dev, stream=stream)
         g.sweep(10)
         g.moments()
         torch.cuda.synchronize()
@@ -362,7 +364,7 @@ def graph_throughput(sweeps, stream, dev):
         dt = time.perf_counter() - t0
         rec = g.moments()
         g.close()
-        out[name] = {"sites": n, "bonds": len(bonds[0]), "T": T, "spin_updates_per_s": n * sweeps / dt,
+        out[name] = {"model": model, "sites": n, "bonds": len(bonds[0]), "T": T, "spin_updates_per_s": n * sweeps / dt,
                      "us_per_sweep": dt / sweeps * 1e6, "mean_m2": float(rec["m2"].mean())}
     out.update(workload="ising_graph_path", sweeps=sweeps)
     return out
