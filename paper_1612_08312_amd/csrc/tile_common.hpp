@@ -609,6 +609,8 @@ enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 // hooked under, and its entry (itself) is already its canonical form.
 constexpr int kTileRoots = 1024;  // LDS root table of the unite pass
 
+constexpr int kForestThreads = 512;  // threads per tile in the unite and store passes
+
 __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid)
 {
     constexpr int H = kTileRoots;     // root slots
@@ -619,7 +621,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     __shared__ int16_t PA[kMaxListed], PB[kMaxListed];
     __shared__ int nroots, missed;
     const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
-    for (int k = tid; k < H; k += kBlock) {
+    for (int k = tid; k < H; k += kForestThreads) {
         HK[k] = -1;
         HP[k] = k;
         BEST[k] = ~0ull;
@@ -640,7 +642,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         }
         return -1;
     };
-    for (int k = tid; k < n; k += kBlock) {
+    for (int k = tid; k < n; k += kForestThreads) {
         const int2 p = list[k];
         const int ra = name_root(lab, p.x), rb = name_root(lab, p.y);
         const int sa = ra == rb ? -1 : insert(ra), sb = ra == rb ? -1 : insert(rb);
@@ -664,7 +666,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         return x;
     };
     const int nl = min(n, kMaxListed);
-    for (int k = tid; k < nl; k += kBlock) {
+    for (int k = tid; k < nl; k += kForestThreads) {
         int a = PA[k], b = PB[k];
         if (a < 0) continue;
         for (int it = 0; it < H; ++it) {
@@ -682,7 +684,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         }
     }
     __syncthreads();
-    for (int s = tid; s < H; s += kBlock) {
+    for (int s = tid; s < H; s += kForestThreads) {
         if (HK[s] < 0) continue;
         atomicMin(&BEST[slot_find(s)], (uint64_t)HK[s] << 10 | (uint64_t)s);
     }
@@ -692,7 +694,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     // slot's list position.
     const bool with_reps = list_stride >= 2 + 2 * H;
     if (!missed) {
-        for (int s = tid; s < H; s += kBlock) {
+        for (int s = tid; s < H; s += kForestThreads) {
             if (HK[s] < 0) continue;
             const int j = atomicAdd(&nroots, 1);
             PA[s] = (int16_t)j;
@@ -700,7 +702,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         }
     }
     __syncthreads();
-    for (int s = tid; s < H; s += kBlock) {
+    for (int s = tid; s < H; s += kForestThreads) {
         if (HK[s] < 0) continue;
         const int rs = (int)(BEST[slot_find(s)] & (uint64_t)(H - 1));
         if (!missed && with_reps) head[2 + H + PA[s]] = PA[rs];
@@ -710,7 +712,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
 }
 
 template <int PASS>
-__global__ __launch_bounds__(kBlock) void k_forest(Chain c)
+__global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
 {
     constexpr int H = kTileRoots;
     __shared__ int HK[PASS == kPassUnite ? 1 : H];
@@ -733,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
         // with group representatives: one walk per group, then plain stores
         const int m = -nroots;
         const int *rp = head + 2 + H;
-        for (int k = tid; k < m; k += kBlock) {
+        for (int k = tid; k < m; k += kForestThreads) {
             if (rp[k] != k) continue;
             const int r = head[2 + k];
             const int e = encoded_canon(lab, r);
@@ -741,12 +743,12 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
             lab_store(lab, r, e);
         }
         __syncthreads();
-        for (int k = tid; k < m; k += kBlock)
+        for (int k = tid; k < m; k += kForestThreads)
             if (rp[k] != k) lab_store(lab, head[2 + k], HK[rp[k]]);
         return;
     }
     if (nroots > 0) {
-        for (int k = tid; k < nroots; k += kBlock) {
+        for (int k = tid; k < nroots; k += kForestThreads) {
             const int r = head[2 + k];
             lab_store(lab, r, encoded_canon(lab, r));
         }
@@ -754,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
     }
     // The list kept its pairs: store once per distinct local root, found
     // through an LDS hash table (a full table stores directly).
-    for (int k = tid; k < H; k += kBlock) HK[k] = -1;
+    for (int k = tid; k < H; k += kForestThreads) HK[k] = -1;
     __syncthreads();
     auto add = [&](int key) {
         uint32_t h = (uint32_t)key * 0x9E3779B1u;
@@ -767,12 +769,12 @@ __global__ __launch_bounds__(kBlock) void k_forest(Chain c)
         }
         lab_store(lab, key, encoded_canon(lab, key));
     };
-    for (int k = tid; k < 2 * n; k += kBlock) {
+    for (int k = tid; k < 2 * n; k += kForestThreads) {
         const int2 p = list[k >> 1];
         add(name_root(lab, (k & 1) ? p.y : p.x));
     }
     __syncthreads();
-    for (int k = tid; k < H; k += kBlock) {
+    for (int k = tid; k < H; k += kForestThreads) {
         const int key = HK[k];
         if (key >= 0) lab_store(lab, key, encoded_canon(lab, key));
     }
