@@ -189,7 +189,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
 
 // Records and state: energy partials (state before this sweep) into the
 // pending record, magnetisation of the new state into a new record.
-__global__ __launch_bounds__(kBlock) void k_finalize_ising(Chain c)
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_ising(Chain c)
 {
     __shared__ int64_t red[16];
     const int rep = blockIdx.x;
@@ -308,7 +308,7 @@ hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &
     if (e == hipSuccess) e = launch_coins(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<IsingFlip>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
-    PYRO_LAUNCH(kKFinalize, k_finalize_ising, c.nreps, kBlock, c);
+    PYRO_LAUNCH(kKFinalize, k_finalize_ising, c.nreps, kFinalizeThreads, c);
     return hipSuccess;
 }
 

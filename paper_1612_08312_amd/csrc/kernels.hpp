@@ -28,6 +28,7 @@ struct DevRecord {
 };
 
 constexpr int kBlock = 256;  // threads of the per-cell and per-call kernels
+constexpr int kFinalizeThreads = 1024;  // one workgroup per replica sums its partials
 
 __host__ __device__ inline int blocks_for(int64_t n, int per_block = kBlock) { return (int)((n + per_block - 1) / per_block); }
 

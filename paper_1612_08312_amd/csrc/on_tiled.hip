@@ -299,7 +299,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
 
 // Records and state (see k_finalize_ising).
 template <int NV>
-__global__ __launch_bounds__(kBlock) void k_finalize_on(Chain c)
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_on(Chain c)
 {
     __shared__ double red[16];
     const int rep = blockIdx.x;
@@ -419,7 +419,7 @@ static hipError_t sweep_on(const Chain &c, hipStream_t st, const LaunchHook &hoo
     if (e == hipSuccess) e = launch_coins(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<OnFlip<NV>>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
-    PYRO_LAUNCH(kKFinalize, k_finalize_on<NV>, c.nreps, kBlock, c);
+    PYRO_LAUNCH(kKFinalize, k_finalize_on<NV>, c.nreps, kFinalizeThreads, c);
     return hipSuccess;
 }
 
