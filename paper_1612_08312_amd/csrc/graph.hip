@@ -409,7 +409,10 @@ hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStrea
         k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
     }
     k_graph_local<<<blocks_for(g.N, kWindow), kLocalThreads, 0, st>>>(g, t);
-    if (g.n_cross > 0) k_graph_cross<<<part_grid(g.n_cross), kBlock, 0, st>>>(g, t);
+    // the cross pass writes no partials (its bond sum goes to an atomic), so
+    // its grid may exceed kPartBlocks: more bonds in flight hide the chases
+    if (g.n_cross > 0)
+        k_graph_cross<<<(int)std::min<int64_t>(blocks_for(g.n_cross), 8 * kPartBlocks), kBlock, 0, st>>>(g, t);
     k_graph_flip<<<part_grid(g.N), kBlock, 0, st>>>(g, t);
     if (nbb > 0 && g.n > 1) k_graph_energy<<<part_grid(g.NB), kBlock, 0, st>>>(g);
     k_graph_finalize<<<1, kBlock, 0, st>>>(g, t, slot);
