@@ -53,7 +53,7 @@ def bytes_per_site(shape):
 # each scaled by the same counter's reading for the probe's 256 MiB copy.
 # Valid only for the kernel sources they were taken with (fingerprint).
 MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
-    "local": ("f85780fa6a7d5033", 216836736),  # profiles/k_local_ising_L128_traffic.md
+    "local": ("8776d9e207800e96", 216838352),  # profiles/k_local_ising_L128_traffic.md
 }
 
 
