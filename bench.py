@@ -399,7 +399,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent lattices would shard by replica; see the design notes)", file=sys.stderr)
+              "(independent lattices would shard by replica, one lattice as slabs along z)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
