@@ -352,6 +352,11 @@ int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls
  * pyro_sw_bonds writes the pyrochlore bond table of edge L (n = 48 L^3
  * entries per array, bond 48 cell + 6 t + e as in the site numbering above)
  * into host arrays.
+ * pyro_sw_sc_bonds writes the periodic simple-cubic table of edge L, the
+ * comparison lattice of Sec. 3.4 (coordination 6 like the pyrochlore):
+ * site (z L + y) L + x, bond 3 i + d joins site i to its +x, +y, +z
+ * neighbour for d = 0, 1, 2 (n = 3 L^3 entries per array; L in [1, 1290],
+ * EINVAL otherwise or for a wrong n or NULL arrays).  Host code, no device.
  */
 typedef struct pyro_sw_graph pyro_sw_graph;
 int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, const int32_t *bond_a,
@@ -364,6 +369,7 @@ int pyro_sw_graph_get_labels(pyro_sw_graph *g, int32_t *host, size_t n);
 int pyro_sw_graph_set_temperature(pyro_sw_graph *g, double T);
 int pyro_sw_graph_destroy(pyro_sw_graph *g);
 int pyro_sw_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n);
+int pyro_sw_sc_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n);
 
 /* Synchronise and free everything the library allocated.  NULL is a no-op. */
 int pyro_sw_destroy(pyro_sw *h);

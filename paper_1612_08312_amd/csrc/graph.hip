@@ -737,4 +737,21 @@ int pyro_sw_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n)
     return PYRO_OK;
 }
 
+int pyro_sw_sc_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n)
+{
+    // L^3 sites below 2^31 and 3 L^3 bonds in an int64 count: L <= 1290.
+    if (L < 1 || L > 1290) return gfail(PYRO_EINVAL, "L must be in [1, 1290]");
+    const int64_t ns = (int64_t)L * L * L;
+    if (!bond_a || !bond_b || n != 3 * ns) return gfail(PYRO_EINVAL, "n must equal 3 L^3");
+    for (int64_t i = 0; i < ns; ++i) {
+        const int64_t x = i % L, y = (i / L) % L, z = i / ((int64_t)L * L);
+        const int64_t xp = x + 1 == L ? 0 : x + 1, yp = y + 1 == L ? 0 : y + 1, zp = z + 1 == L ? 0 : z + 1;
+        bond_a[3 * i] = bond_a[3 * i + 1] = bond_a[3 * i + 2] = (int32_t)i;
+        bond_b[3 * i] = (int32_t)((z * L + y) * L + xp);
+        bond_b[3 * i + 1] = (int32_t)((z * L + yp) * L + x);
+        bond_b[3 * i + 2] = (int32_t)((zp * L + y) * L + x);
+    }
+    return PYRO_OK;
+}
+
 }  // extern "C"

@@ -611,6 +611,13 @@ constexpr int kTileRoots = 1024;  // LDS root table of the unite pass
 
 constexpr int kForestThreads = 512;  // threads per tile in the unite and store passes
 
+// LDS words that other threads of the workgroup change concurrently (root
+// tables and parent slots of the unite and store passes) are read and
+// written with relaxed workgroup-scope atomics, so that no load is hoisted
+// out of a retry loop or served from a register copy.
+__device__ __forceinline__ int lds_ld(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ void lds_st(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
 __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid)
 {
     constexpr int H = kTileRoots;     // root slots
@@ -636,7 +643,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         h ^= h >> 15;
         for (int probe = 0; probe < 32; ++probe) {
             const int slot = (int)((h + (uint32_t)probe) & (H - 1));
-            int prev = HK[slot];
+            int prev = lds_ld(&HK[slot]);
             if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
             if (prev == -1 || prev == key) return slot;
         }
@@ -657,10 +664,10 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     __syncthreads();
     auto slot_find = [&](int x) {
         for (int it = 0; it < H; ++it) {
-            const int p = HP[x];
+            const int p = lds_ld(&HP[x]);
             if (p == x) return x;
-            const int gp = HP[p];
-            if (gp != p) HP[x] = gp;
+            const int gp = lds_ld(&HP[p]);
+            if (gp != p) lds_st(&HP[x], gp);
             x = p;
         }
         return x;
@@ -763,7 +770,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
         h ^= h >> 15;
         for (int probe = 0; probe < 32; ++probe) {
             const int slot = (int)((h + (uint32_t)probe) & (H - 1));
-            int prev = HK[slot];
+            int prev = lds_ld(&HK[slot]);
             if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
             if (prev == -1 || prev == key) return;
         }

@@ -50,7 +50,7 @@ EXPORTS = (
     "pyro_sw_philox_rate",
     "pyro_sw_graph_init", "pyro_sw_graph_sweep", "pyro_sw_graph_moments", "pyro_sw_graph_get_spins",
     "pyro_sw_graph_set_spins", "pyro_sw_graph_get_labels", "pyro_sw_graph_set_temperature",
-    "pyro_sw_graph_destroy", "pyro_sw_bonds",
+    "pyro_sw_graph_destroy", "pyro_sw_bonds", "pyro_sw_sc_bonds",
 )
 
 PYRO_JOB_QUEUED, PYRO_JOB_RUNNING, PYRO_JOB_DONE = 0, 1, 2
@@ -142,6 +142,7 @@ def load_library():
     lib.pyro_sw_graph_set_temperature.argtypes = [vp, f64]
     lib.pyro_sw_graph_destroy.argtypes = [vp]
     lib.pyro_sw_bonds.argtypes = [i32, vp, vp, i64]
+    lib.pyro_sw_sc_bonds.argtypes = [i32, vp, vp, i64]
     lib.pyro_sw_strerror.argtypes = [i32]
     lib.pyro_sw_strerror.restype = ctypes.c_char_p
     lib.pyro_sw_last_error.argtypes = []
@@ -546,16 +547,14 @@ def pyro_sw_bonds(L: int):
 
 
 def simple_cubic_bonds(L: int):
-    """Simple-cubic bond table of edge L, periodic: site (z L + y) L + x, bond
-    3 i + d to its +x, +y, +z neighbour (d = 0, 1, 2)."""
-    L = int(L)
-    i = np.arange(L ** 3, dtype=np.int64)
-    x, y, z = i % L, (i // L) % L, i // (L * L)
-    nb = np.stack([(z * L + y) * L + (x + 1) % L,
-                   (z * L + (y + 1) % L) * L + x,
-                   (((z + 1) % L) * L + y) * L + x], axis=1)
-    a = np.repeat(i, 3).astype(np.int32)
-    return a, nb.reshape(-1).astype(np.int32)
+    """Simple-cubic bond table of edge L, periodic (pyro_sw_sc_bonds): site
+    (z L + y) L + x, bond 3 i + d to its +x, +y, +z neighbour (d = 0, 1, 2)."""
+    n = 3 * int(L) ** 3
+    a = np.zeros(n, np.int32)
+    b = np.zeros(n, np.int32)
+    _check(load_library().pyro_sw_sc_bonds(int(L), a.ctypes.data_as(ctypes.c_void_p),
+                                           b.ctypes.data_as(ctypes.c_void_p), n), "pyro_sw_sc_bonds")
+    return a, b
 
 
 class Graph:

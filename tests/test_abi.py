@@ -108,8 +108,8 @@ def test_philox_rate_null_outputs():
 
 
 def test_bond_tables_match_the_oracle():
-    """pyro_sw_bonds (host code of the library) and the package's simple-cubic
-    table give the oracle's bond lists, bond for bond."""
+    """pyro_sw_bonds and pyro_sw_sc_bonds (host code of the library) give the
+    oracle's bond lists, bond for bond."""
     import numpy as np
 
     import oracle
@@ -126,6 +126,12 @@ def test_bond_tables_match_the_oracle():
         np.testing.assert_array_equal(b, ob)
     with pytest.raises(pyrosw.PyroSWError):
         pyrosw.pyro_sw_bonds(0)
+    with pytest.raises(pyrosw.PyroSWError):
+        pyrosw.simple_cubic_bonds(0)
+    lib = pyrosw.load_library()
+    a = np.zeros(3 * 8, np.int32)
+    assert lib.pyro_sw_sc_bonds(2, a.ctypes.data, a.ctypes.data, 3 * 8 - 1) == pyrosw.PYRO_EINVAL
+    assert lib.pyro_sw_sc_bonds(2, None, a.ctypes.data, 3 * 8) == pyrosw.PYRO_EINVAL
 
 
 @pytest.mark.parametrize("bonds,n,model", [

@@ -126,20 +126,71 @@ def test_ising_from_seeded_configuration():
     np.testing.assert_array_equal(g.labels(), o.labels())
 
 
-def test_ising_l128_first_sweeps_bit_exact():
-    """Full-size lattice (33,554,432 sites): the first three sweeps from the
-    random start, at the centre temperature of the five-temperature run."""
+# Oracle results of the five full-size lattices (three sweeps each), kept for
+# the group test below: records, spins and labels after the third sweep.
+_L128_ORACLE = {}
+
+
+def l128_oracle(k):
+    """Records of the first three sweeps of lattice k of the five-temperature
+    L = 128 workload, with its spins and labels after sweeps 2 and 3."""
+    if k not in _L128_ORACLE:
+        c = workloads.ISING_L128
+        o = oracle.Oracle(L=128, model=1, T=c["temps"][k], seed=c["seeds"][k], start=c["start"])
+        s0 = o.spins()
+        r2 = o.sweep(2)
+        s2, l2 = o.spins(), o.labels()
+        r3 = o.sweep(1)
+        _L128_ORACLE[k] = dict(s0=s0, rec=np.concatenate([r2, r3]), s2=s2, l2=l2, s3=o.spins(), l3=o.labels())
+        del o
+    return _L128_ORACLE[k]
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_ising_l128_first_sweeps_bit_exact(k):
+    """Full-size lattice (33,554,432 sites) at each of the five temperatures
+    of the workload: three sweeps from the random start.  The first call runs
+    two sweeps, so the energy of the first record comes from the bond count
+    fused into the second sweep's tile pass; the last record's energy comes
+    from the tail pass of the drain."""
     c = workloads.ISING_L128
-    T, seed = c["temps"][2], c["seeds"][2]
+    T, seed = c["temps"][k], c["seeds"][k]
+    ref = l128_oracle(k)
     g = gpu_lattice(L=128, model=1, T=T, seed=seed, start=c["start"])
-    o = oracle.Oracle(L=128, model=1, T=T, seed=seed, start=c["start"])
-    np.testing.assert_array_equal(g.spins(), o.spins())
-    for _ in range(3):
-        g.sweep(1)
-        assert_records_exact(g.moments(), o.sweep(1))
-        np.testing.assert_array_equal(g.labels(), o.labels())
-        np.testing.assert_array_equal(g.spins(), o.spins())
-        say("L=128 sweep ok")
+    np.testing.assert_array_equal(g.spins(), ref["s0"])
+    g.sweep(2)
+    assert_records_exact(g.moments(), ref["rec"][:2])
+    np.testing.assert_array_equal(g.labels(), ref["l2"])
+    np.testing.assert_array_equal(g.spins(), ref["s2"])
+    g.sweep(1)
+    assert_records_exact(g.moments(), ref["rec"][2:])
+    np.testing.assert_array_equal(g.labels(), ref["l3"])
+    np.testing.assert_array_equal(g.spins(), ref["s3"])
+    g.close()
+    say(f"L=128 T={T}: three sweeps bit-exact")
+
+
+def test_ising_l128_benched_group_form_bit_exact():
+    """The form the benchmark times: the five L = 128 lattices in one group,
+    autotuned, in concurrent slices (one captured graph each), three sweeps
+    in one call (no drain between them).  Every member's records (energies
+    included), spins and labels equal the oracle's."""
+    c = workloads.ISING_L128
+    lats = [gpu_lattice(L=128, model=1, T=T, seed=s, start=c["start"]) for T, s in zip(c["temps"], c["seeds"])]
+    grp = pyrosw.Group(lats)
+    shapes = grp.autotune(trial_sweeps=3)
+    say("benched group form: autotuned tile shape", pyrosw.TILE_SHAPES[shapes[0]])
+    grp.sweep(3)
+    for k, lt in enumerate(lats):
+        ref = l128_oracle(k)
+        assert_records_exact(lt.moments(), ref["rec"])
+        np.testing.assert_array_equal(lt.spins(), ref["s3"])
+        np.testing.assert_array_equal(lt.labels(), ref["l3"])
+        say(f"benched group form: member {k} bit-exact")
+    grp.close()
+    for lt in lats:
+        lt.close()
+    _L128_ORACLE.clear()
 
 
 @pytest.mark.parametrize("model,L,T", [(2, 3, 2.0285), (3, 3, 1.31695), (2, 8, 2.0285), (3, 8, 1.31695),
@@ -157,15 +208,19 @@ def test_on_cold_start_and_infinite_temperature():
     np.testing.assert_array_equal(g.labels(), np.arange(g.N))
 
 
-def test_on_l64_first_sweeps():
-    """Full-size O(n) lattices (4,194,304 sites): first sweeps within 1e-5."""
-    for c in workloads.ON_L64:
-        g = gpu_lattice(L=c["L"], model=c["model"], T=c["T"], seed=c["seed"], start=c["start"])
-        o = oracle.Oracle(L=c["L"], model=c["model"], T=c["T"], seed=c["seed"], start=c["start"])
-        g.sweep(3)
-        assert_records_close(g.moments(), o.sweep(3))
+@pytest.mark.parametrize("which", [0, 1])
+def test_on_l64_first_sweeps(which):
+    """Full-size O(n) lattices (4,194,304 sites): the first 20 sweeps, records
+    within 1e-5, labels bit-exact, spins within 1e-5 after sweeps 10 and 20."""
+    c = workloads.ON_L64[which]
+    g = gpu_lattice(L=c["L"], model=c["model"], T=c["T"], seed=c["seed"], start=c["start"])
+    o = oracle.Oracle(L=c["L"], model=c["model"], T=c["T"], seed=c["seed"], start=c["start"])
+    for _ in range(2):
+        g.sweep(10)
+        assert_records_close(g.moments(), o.sweep(10))
         np.testing.assert_array_equal(g.labels(), o.labels())
         np.testing.assert_allclose(g.spins(), o.spins(), rtol=0, atol=1e-5)
+        say("O(n) L=64: ten more sweeps within tolerance")
 
 
 def test_determinism_repeat():
