@@ -41,8 +41,7 @@ def bytes_per_site(shape):
         "local": 1.0 + 4.0,            # read spins, write tile-local roots
         "unite": 0.0,                  # forest walks over the crossing lists (data dependent)
         "canon_store": 0.0,            # idem
-        "coins": 1.0 / 8,              # write one flip coin per site
-        "flip": 4.0 + 1.0 + 1.0 + 1.0 / 8,  # read labels, read and write spins, read coins
+        "flip": 4.0 + 1.0 + 1.0,       # read labels, read and write spins (coins are drawn in the kernel)
         "energy": 1.0,                 # read spins
         "finalize": 0.0,
     }

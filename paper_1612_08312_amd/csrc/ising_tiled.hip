@@ -10,12 +10,13 @@
 //                  write every site's tile-local root as a global site index
 //                  and list the tile's crossing pairs (tile_components).  The
 //                  parallel-bond count is the energy of the incoming state.
-//   k_forest       unite, minimum and store passes over the crossing lists
-//                  (tile_common.hpp).
-//   k_coins        flip coins (tile_common.hip).
-//   k_flip_ising   one workgroup per tile: canonical label of every site from
-//                  an LDS copy of the tile's labels, coin, XOR flip of the
-//                  int8 spins, magnetisation of the new state.
+//   k_forest       unite and store passes over the crossing lists
+//                  (tile_common.hpp); the store pass writes each merged
+//                  cluster's smallest site and flip coin into its local roots.
+//   k_flip_ising   one workgroup per tile: the coin of every site's cluster
+//                  from an LDS copy of the tile's labels and the tile's own
+//                  coins, XOR flip of the int8 spins, magnetisation of the new
+//                  state.
 //   k_finalize_ising  fixed-order sums of the partials into the records,
 //                  then advance the replica's state.
 // Local site order inside a tile follows the global order, so a tile-local
@@ -105,18 +106,20 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     if (tid == 0) d.ipart[tile] = bsum;
 }
 
-// One workgroup per tile: the labels of the tile's sites are staged in LDS,
-// so the canonical label of every site (site -> local root, both in the
-// tile) costs no scattered global read; then coins, flips and the
-// magnetisation of the new state.
+// One workgroup per tile: the labels of the tile's sites and the coins of
+// its own clusters are staged in LDS, so the coin of every site's cluster
+// (site -> local root -> stored encoding or the root's own coin) costs no
+// scattered global read; then flips and the magnetisation of the new state.
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
     __shared__ int LAB[16 * NC];
+    __shared__ uint32_t CB[NC];
     __shared__ int64_t red[16];
     const int rep = c.tile_rep[blockIdx.x];
-    if (c.state[rep]->remaining <= 0) return;
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
@@ -140,30 +143,11 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
 #pragma unroll
         for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
     }
+    CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
     __syncthreads();
     int mag = 0;
     if (valid) {
-        const uint32_t *__restrict__ fb = d.coins;
-        int last_in = -1, last_c = -1;
-        uint32_t flipmask = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int r0 = lab[k];  // tile-local root, or an encoded canonical label
-            int cl;
-            if (r0 < 0) {
-                cl = r0 - kCanonBase;  // the site is a merged local root
-            } else if (r0 & kTag) {
-                cl = r0 & kIdxMask;  // not produced by a complete sweep; kept in range
-            } else if (r0 == last_in) {
-                cl = last_c;
-            } else {
-                const int v = LAB[lds_pos<NC>(ti.local_key(r0))];
-                cl = v < 0 ? v - kCanonBase : (v & kIdxMask);
-                last_in = r0;
-                last_c = cl;
-            }
-            flipmask |= ((fb[cl >> 5] >> (cl & 31)) & 1u) << k;
-        }
+        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, st.t, d.key);
         int4 *S4 = reinterpret_cast<int4 *>(d.spins);
         const int4 sv = S4[cell];
         uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
@@ -305,7 +289,6 @@ hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &
 {
     hipError_t e = with_tile_shape<IsingLocal>(c.shape, c, st, hook);
     if (e == hipSuccess) e = launch_merge(c, st, hook);
-    if (e == hipSuccess) e = launch_coins(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<IsingFlip>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
     PYRO_LAUNCH(kKFinalize, k_finalize_ising, c.nreps, kFinalizeThreads, c);

@@ -50,7 +50,6 @@ struct RepDesc {
     // device buffers owned by the replica
     void *spins;       // int8 [N] or float [n][N]
     int32_t *label;    // [N]
-    uint32_t *coins;   // [4 ceil(N/128)] flip coins of the current sweep
     int64_t *ipart;    // integer partial sums
     double *dpart;     // FP64 partial sums
     float *axis;       // [4] embedding axis of the current sweep
@@ -69,7 +68,7 @@ struct RepDesc {
     int mpart_off;  // per-tile magnetisation partials start here in ipart / dpart
     int tail_off;   // per-cell-block partials of the energy tail start here
     // first block of this replica in each grid of its chain
-    int tile_base, cblk_base, coin_base;
+    int tile_base, cblk_base;
 };
 
 struct RepState {
@@ -80,17 +79,16 @@ struct RepState {
 };
 
 // What every chain kernel receives: descriptors, states and the block ->
-// replica maps of the three grids.
+// replica maps of the two grids.
 struct Chain {
     const RepDesc *desc;
     RepState *const *state;  // state of each replica (in its own workspace)
     const int *tile_rep;  // tile grid
     const int *cblk_rep;  // 256-cell blocks
-    const int *coin_rep;  // 256-call blocks of the coin kernel
     int nreps;
     int shape;            // TileShape of the tile grid
     int model;            // 1, 2, 3
-    int ntile_blocks, ncell_blocks, ncoin_blocks;
+    int ntile_blocks, ncell_blocks;
 };
 
 // Kernel ids for timing (names in init.hip).
@@ -98,7 +96,6 @@ enum KernelId : int {
     kKInit = 0,
     kKLocal,     // tile pass
     kKUnite,     // forest unite pass
-    kKCoins,
     kKFlip,
     kKEnergy,    // energy tail
     kKFinalize,

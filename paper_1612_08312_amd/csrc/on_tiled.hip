@@ -189,16 +189,19 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     if (tid == 0) d.dpart[tile] = b;
 }
 
-// One workgroup per tile: canonical labels from an LDS copy of the tile's
-// labels (as in the Ising flip), coins, reflections, FP64 magnetisation.
+// One workgroup per tile: cluster coins from an LDS copy of the tile's
+// labels and the tile's own coins (as in the Ising flip), reflections, FP64
+// magnetisation.
 template <int NV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
     __shared__ int LAB[16 * NC];
+    __shared__ uint32_t CB[NC];
     __shared__ double red[16];
     const int rep = c.tile_rep[blockIdx.x];
-    if (c.state[rep]->remaining <= 0) return;
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
 #pragma unroll
         for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
     }
+    CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
     __syncthreads();
     double M[NV];
 #pragma unroll
@@ -232,27 +236,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
         float r[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
-        const uint32_t *__restrict__ fb = d.coins;
-        int last_in = -1, last_c = -1;
-        uint32_t flipmask = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int r0 = lab[k];
-            int cl;
-            if (r0 < 0) {
-                cl = r0 - kCanonBase;  // the site is a merged local root
-            } else if (r0 & kTag) {
-                cl = r0 & kIdxMask;  // not produced by a complete sweep; kept in range
-            } else if (r0 == last_in) {
-                cl = last_c;
-            } else {
-                const int v = LAB[lds_pos<NC>(ti.local_key(r0))];
-                cl = v < 0 ? v - kCanonBase : (v & kIdxMask);
-                last_in = r0;
-                last_c = cl;
-            }
-            flipmask |= ((fb[cl >> 5] >> (cl & 31)) & 1u) << k;
-        }
+        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, st.t, d.key);
         float v[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -416,7 +400,6 @@ static hipError_t sweep_on(const Chain &c, hipStream_t st, const LaunchHook &hoo
     PYRO_LAUNCH(kKAxis, k_axis, c.nreps, 64, c);
     hipError_t e = with_tile_shape<OnLocal<NV>>(c.shape, c, st, hook);
     if (e == hipSuccess) e = launch_merge(c, st, hook);
-    if (e == hipSuccess) e = launch_coins(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<OnFlip<NV>>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
     PYRO_LAUNCH(kKFinalize, k_finalize_on<NV>, c.nreps, kFinalizeThreads, c);

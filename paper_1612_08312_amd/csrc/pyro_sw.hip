@@ -84,11 +84,9 @@ int64_t max_tiles(int L)
     return m;
 }
 
-int64_t coin_calls(int64_t N) { return (N + 127) / 128; }
-
 struct Layout {
     size_t spin_bytes;
-    size_t label, coins, ipart, dpart, axis, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
+    size_t label, ipart, dpart, axis, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
     int64_t map_len;
 };
 
@@ -105,7 +103,6 @@ Layout layout_for(int L, int model)
         return at;
     };
     ly.label = take(sizeof(int32_t) * (size_t)N);
-    ly.coins = take(16 * (size_t)coin_calls(N));
     ly.ipart = take(sizeof(int64_t) * (size_t)ipart_count(L));
     ly.dpart = take(model == PYRO_ISING ? 0 : sizeof(double) * (size_t)dpart_count(L));
     ly.axis = take(4 * sizeof(float));
@@ -114,7 +111,7 @@ Layout layout_for(int L, int model)
     ly.state = take(sizeof(RepState));
     ly.solo_desc = take(sizeof(RepDesc));
     ly.solo_stp = take(sizeof(RepState *));
-    ly.map_len = std::max<int64_t>({max_tiles(L), blocks_for(ncell), blocks_for(coin_calls(N))});
+    ly.map_len = std::max<int64_t>(max_tiles(L), blocks_for(ncell));
     ly.solo_map = take(sizeof(int) * (size_t)ly.map_len);
     ly.total = off;
     return ly;
@@ -216,7 +213,7 @@ struct ChainTables {
     std::vector<pyro_sw *> reps;
     RepDesc *d_desc = nullptr;
     RepState **d_stp = nullptr;
-    int *d_tile_rep = nullptr, *d_cblk_rep = nullptr, *d_coin_rep = nullptr;
+    int *d_tile_rep = nullptr, *d_cblk_rep = nullptr;
     Chain chain{};
     bool owned = true;       // tables in `block` (groups) or in a workspace (solo)
     void *block = nullptr;   // stream-ordered allocation holding a group's tables
@@ -299,15 +296,22 @@ int device_fail(bool *broken, hipError_t e, const char *what)
         if (e__ != hipSuccess) return device_fail(flag, e__, #call);     \
     } while (0)
 
+// The two per-run constants of Sec. 2: Ising threshold floor((1 -
+// exp(-2J/T)) 2^32), split at bit 24, and the O(n) coupling (float)(2J/T).
+void run_constants(double T, double J, uint32_t *thr_hi, uint32_t *thr_lo, float *x0)
+{
+    const double twobj = 2.0 * J / T;
+    const double p = -expm1(-twobj);
+    const uint64_t thr = (uint64_t)floor(p * 4294967296.0);
+    *thr_hi = (uint32_t)(thr >> 24);
+    *thr_lo = (uint32_t)(thr & 0xFFFFFFu);
+    *x0 = (float)twobj;
+}
+
 void set_params(pyro_sw *h, double T)
 {
     h->T = T;
-    const double twobj = 2.0 * h->J / T;
-    const double p = -expm1(-twobj);
-    const uint64_t thr = (uint64_t)floor(p * 4294967296.0);
-    h->thr_hi = (uint32_t)(thr >> 24);
-    h->thr_lo = (uint32_t)(thr & 0xFFFFFFu);
-    h->x0 = (float)twobj;
+    run_constants(T, h->J, &h->thr_hi, &h->thr_lo, &h->x0);
     h->param_version++;
 }
 
@@ -330,39 +334,47 @@ void present_masks(const int8_t *s, int L, std::vector<uint64_t> &pm)
     }
 }
 
-// Descriptor of a replica for a chain with tile shape `shape`.
-RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base, int coin_base)
+// Descriptor of a lattice (edge L, model, run constants, spins and a
+// workspace laid out by layout_for) for a chain with tile shape `shape`.
+RepDesc lattice_desc(int L, int model, double J, uint64_t seed, uint32_t thr_hi, uint32_t thr_lo, float x0,
+                     void *spins, char *work, const Layout &ly, const uint64_t *present, int shape, int tile_base,
+                     int cblk_base)
 {
     RepDesc d{};
     const TileDims t = tile_dims(shape);
-    d.L = h->L;
-    d.ntx = (h->L + t.x - 1) / t.x;
-    d.nty = (h->L + t.y - 1) / t.y;
-    d.ntz = (h->L + t.z - 1) / t.z;
-    d.ncell = h->ncell;
-    d.N = h->N;
-    d.spins = h->spins;
-    d.label = (int32_t *)(h->work + h->ly.label);
-    d.coins = (uint32_t *)(h->work + h->ly.coins);
-    d.ipart = (int64_t *)(h->work + h->ly.ipart);
-    d.dpart = h->model == PYRO_ISING ? nullptr : (double *)(h->work + h->ly.dpart);
-    d.axis = (float *)(h->work + h->ly.axis);
-    d.ring = (DevRecord *)(h->work + h->ly.ring);
-    d.pairs = (int *)(h->work + h->ly.pairs);
+    d.L = L;
+    d.ntx = (L + t.x - 1) / t.x;
+    d.nty = (L + t.y - 1) / t.y;
+    d.ntz = (L + t.z - 1) / t.z;
+    d.ncell = (int64_t)L * L * L;
+    d.N = 16 * d.ncell;
+    d.spins = spins;
+    d.label = (int32_t *)(work + ly.label);
+    d.ipart = (int64_t *)(work + ly.ipart);
+    d.dpart = model == PYRO_ISING ? nullptr : (double *)(work + ly.dpart);
+    d.axis = (float *)(work + ly.axis);
+    d.ring = (DevRecord *)(work + ly.ring);
+    d.pairs = (int *)(work + ly.pairs);
     d.list_stride = tile_list_stride(shape);
-    d.present = h->diluted ? h->d_present : nullptr;
-    d.thr_hi = h->thr_hi;
-    d.thr_lo = h->thr_lo;
-    d.x0 = h->x0;
-    d.J = h->J;
-    d.key = philox_key(h->seed);
+    d.present = present;
+    d.thr_hi = thr_hi;
+    d.thr_lo = thr_lo;
+    d.x0 = x0;
+    d.J = J;
+    d.key = philox_key(seed);
     d.ring_cap = kRing;
-    d.mpart_off = (int)max_tiles(h->L);
-    d.tail_off = (int)(h->model == PYRO_ISING ? 2 * max_tiles(h->L) : 4 * max_tiles(h->L));
+    d.mpart_off = (int)max_tiles(L);
+    d.tail_off = (int)(model == PYRO_ISING ? 2 * max_tiles(L) : 4 * max_tiles(L));
     d.tile_base = tile_base;
     d.cblk_base = cblk_base;
-    d.coin_base = coin_base;
     return d;
+}
+
+// Descriptor of a replica for a chain with tile shape `shape`.
+RepDesc make_desc(const pyro_sw *h, int shape, int tile_base, int cblk_base)
+{
+    return lattice_desc(h->L, h->model, h->J, h->seed, h->thr_hi, h->thr_lo, h->x0, h->spins, h->work, h->ly,
+                        h->diluted ? h->d_present : nullptr, shape, tile_base, cblk_base);
 }
 
 // Group tables live in one stream-ordered allocation on the group's stream,
@@ -374,7 +386,7 @@ void free_tables(ChainTables &ct)
     ct.block = nullptr;
     ct.d_desc = nullptr;
     ct.d_stp = nullptr;
-    ct.d_tile_rep = ct.d_cblk_rep = ct.d_coin_rep = nullptr;
+    ct.d_tile_rep = ct.d_cblk_rep = nullptr;
 }
 
 // Build (or rebuild) the device tables of a group chain on stream st; the
@@ -393,32 +405,28 @@ hipError_t build_group_chain(ChainTables &ct, int shape, hipStream_t st)
     if (n == 0) return hipSuccess;
     std::vector<RepDesc> desc(n);
     std::vector<RepState *> stp(n);
-    std::vector<int> tmap, cmap, kmap;
-    int tb = 0, cb = 0, kb = 0;
+    std::vector<int> tmap, cmap;
+    int tb = 0, cb = 0;
     for (int r = 0; r < n; ++r) {
         pyro_sw *h = ct.reps[r];
-        desc[r] = make_desc(h, shape, tb, cb, kb);
+        desc[r] = make_desc(h, shape, tb, cb);
         stp[r] = h->d_state;
-        const int nt = (int)tiles_for(h->L, shape), nc = blocks_for(h->ncell), nk = blocks_for(coin_calls(h->N));
+        const int nt = (int)tiles_for(h->L, shape), nc = blocks_for(h->ncell);
         tmap.insert(tmap.end(), nt, r);
         cmap.insert(cmap.end(), nc, r);
-        kmap.insert(kmap.end(), nk, r);
         tb += nt;
         cb += nc;
-        kb += nk;
     }
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_desc = up(sizeof(RepDesc) * n), b_stp = up(sizeof(RepState *) * n);
     const size_t b_t = up(sizeof(int) * tmap.size()), b_c = up(sizeof(int) * cmap.size());
-    const size_t b_k = up(sizeof(int) * kmap.size());
-    hipError_t e = hipMallocAsync(&ct.block, b_desc + b_stp + b_t + b_c + b_k, st);
+    hipError_t e = hipMallocAsync(&ct.block, b_desc + b_stp + b_t + b_c, st);
     if (e != hipSuccess) return e;
     char *p = (char *)ct.block;
     ct.d_desc = (RepDesc *)p;
     ct.d_stp = (RepState **)(p + b_desc);
     ct.d_tile_rep = (int *)(p + b_desc + b_stp);
     ct.d_cblk_rep = (int *)(p + b_desc + b_stp + b_t);
-    ct.d_coin_rep = (int *)(p + b_desc + b_stp + b_t + b_c);
     if ((e = hipMemcpyAsync(ct.d_desc, desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
         return e;
     if ((e = hipMemcpyAsync(ct.d_stp, stp.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -429,18 +437,13 @@ hipError_t build_group_chain(ChainTables &ct, int shape, hipStream_t st)
     if ((e = hipMemcpyAsync(ct.d_cblk_rep, cmap.data(), sizeof(int) * cmap.size(), hipMemcpyHostToDevice, st)) !=
         hipSuccess)
         return e;
-    if ((e = hipMemcpyAsync(ct.d_coin_rep, kmap.data(), sizeof(int) * kmap.size(), hipMemcpyHostToDevice, st)) !=
-        hipSuccess)
-        return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;  // host vectors go out of scope
     ct.chain.desc = ct.d_desc;
     ct.chain.state = ct.d_stp;
     ct.chain.tile_rep = ct.d_tile_rep;
     ct.chain.cblk_rep = ct.d_cblk_rep;
-    ct.chain.coin_rep = ct.d_coin_rep;
     ct.chain.ntile_blocks = tb;
     ct.chain.ncell_blocks = cb;
-    ct.chain.ncoin_blocks = kb;
     return hipSuccess;
 }
 
@@ -452,11 +455,11 @@ hipError_t build_solo_chain(pyro_sw *h)
     ct.model = h->model;
     ct.shape = h->solo_shape;
     ct.reps.assign(1, h);
-    const RepDesc d = make_desc(h, h->solo_shape, 0, 0, 0);
+    const RepDesc d = make_desc(h, h->solo_shape, 0, 0);
     ct.d_desc = (RepDesc *)(h->work + h->ly.solo_desc);
     ct.d_stp = (RepState **)(h->work + h->ly.solo_stp);
     int *zeros = (int *)(h->work + h->ly.solo_map);
-    ct.d_tile_rep = ct.d_cblk_rep = ct.d_coin_rep = zeros;
+    ct.d_tile_rep = ct.d_cblk_rep = zeros;
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return e;
     if ((e = hipMemcpy(ct.d_desc, &d, sizeof(RepDesc), hipMemcpyHostToDevice)) != hipSuccess) return e;
@@ -466,13 +469,12 @@ hipError_t build_solo_chain(pyro_sw *h)
     c = Chain{};
     c.desc = ct.d_desc;
     c.state = ct.d_stp;
-    c.tile_rep = c.cblk_rep = c.coin_rep = zeros;
+    c.tile_rep = c.cblk_rep = zeros;
     c.nreps = 1;
     c.shape = h->solo_shape;
     c.model = h->model;
     c.ntile_blocks = (int)tiles_for(h->L, h->solo_shape);
     c.ncell_blocks = blocks_for(h->ncell);
-    c.ncoin_blocks = blocks_for(coin_calls(h->N));
     if (h->solo_exec) {
         hipGraphExecDestroy(h->solo_exec);
         h->solo_exec = nullptr;
@@ -617,7 +619,7 @@ int create(pyro_sw **out, int L, int model, double T, double J, uint64_t seed, i
         e = hipMemcpy(h->work + ly.solo_map, zeros.data(), sizeof(int) * zeros.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_state, &h->hs, sizeof(RepState), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = build_solo_chain(h);
-    if (e == hipSuccess) e = launch_init(make_desc(h, h->solo_shape, 0, 0, 0), model, start, h->stream);
+    if (e == hipSuccess) e = launch_init(make_desc(h, h->solo_shape, 0, 0), model, start, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         int r = fail(PYRO_EDEVICE, std::string("initial state: ") + hipGetErrorString(e));
@@ -823,7 +825,7 @@ int pyro_sw_get_labels(pyro_sw *h, int32_t *host, size_t n)
     int rc = usable(h);
     if (rc) return rc;
     if (!host || n != (size_t)h->N) return fail(PYRO_EINVAL, "n must equal N");
-    const RepDesc d = make_desc(h, h->solo_shape, 0, 0, 0);
+    const RepDesc d = make_desc(h, h->solo_shape, 0, 0);
     int32_t *tmp = nullptr;
     if (hipMalloc((void **)&tmp, sizeof(int32_t) * n) != hipSuccess) {
         (void)hipGetLastError();

@@ -1,7 +1,6 @@
 // Model-independent launchers of the tiled sweep: the passes over the
-// tiles' crossing lists, the flip coins, the canonical labels the host reads
-// (written to a separate buffer), and the dispatch of one sweep of a chain to
-// its model.
+// tiles' crossing lists, the canonical labels the host reads (written to a
+// separate buffer), and the dispatch of one sweep of a chain to its model.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,21 +13,6 @@
 #include "tile_common.hpp"
 
 namespace pyro {
-
-// 128 flip coins per Philox call: call g of a replica writes coin words
-// 4g .. 4g+3, so the coin of the cluster rooted at site r is bit (r mod 32)
-// of word r/32, i.e. bit (r mod 32) of word ((r/32) mod 4) of FLIP(r/128).
-__global__ __launch_bounds__(kBlock) void k_coins(Chain c)
-{
-    const int rep = c.coin_rep[blockIdx.x];
-    const RepState st = *c.state[rep];
-    if (st.remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    const int64_t g = (int64_t)(blockIdx.x - d.coin_base) * kBlock + threadIdx.x;
-    const int64_t ncalls = (d.N + 127) / 128;
-    if (g >= ncalls) return;
-    reinterpret_cast<uint4 *>(d.coins)[g] = philox4x32_10((uint32_t)g, st.t, kStreamFlip, 0u, d.key);
-}
 
 // Canonical label of every site into `out` (only when the host reads
 // labels; the label array itself is left as the sweep built it, so the walks
@@ -45,12 +29,6 @@ hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
     PYRO_LAUNCH(kKUnite, k_forest<kPassUnite>, c.ntile_blocks, kForestThreads, c);
     PYRO_LAUNCH(kKCompress, k_forest<kPassStore>, c.ntile_blocks, kForestThreads, c);
-    return hipSuccess;
-}
-
-hipError_t launch_coins(const Chain &c, hipStream_t st, const LaunchHook &hook)
-{
-    PYRO_LAUNCH(kKCoins, k_coins, c.ncoin_blocks, kBlock, c);
     return hipSuccess;
 }
 

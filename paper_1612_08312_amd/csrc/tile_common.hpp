@@ -196,8 +196,9 @@ struct TileIdx {
 // encodings of a local root r:
 //   r                   r is a root of the merged forest
 //   kTag | p            r was hooked under p
-//   kCanonBase + c      written by the store pass: c is the smallest site
-//                       index of r's cluster
+//   kCanonBase + c (| kCoinBit)  written by the store pass: c is the
+//                       smallest site index of r's cluster, and kCoinBit is
+//                       set when that cluster flips in this sweep
 // Site indices are below 2^30 (L <= 406), so the three forms are distinct and
 // the local root of any site is decodable at any time, even while other
 // threads hook roots or store canonical labels: an entry that is negative,
@@ -211,6 +212,23 @@ struct TileIdx {
 constexpr int kTag = 1 << 30;
 constexpr int kIdxMask = kTag - 1;
 constexpr int kCanonBase = INT32_MIN;  // canonical index c is stored as kCanonBase + c
+constexpr int kCoinBit = 1 << 30;      // flip coin of the cluster, in a stored encoding
+
+// Flip coin of the cluster whose smallest site is r in sweep t: bit (r mod
+// 32) of word ((r/32) mod 4) of FLIP(r/128).
+__device__ __forceinline__ uint32_t cluster_coin(int r, uint32_t t, PhiloxKey key)
+{
+    const uint4 w = philox4x32_10((uint32_t)r >> 7, t, kStreamFlip, 0u, key);
+    return (word_of(w, ((uint32_t)r >> 5) & 3u) >> (r & 31)) & 1u;
+}
+
+// The coins of the 16 sites of a cell (bit k = site 16 cell + k) in sweep t:
+// sites of one cell are 16 consecutive bits of one word of FLIP(cell/8).
+__device__ __forceinline__ uint32_t cell_coins(int cell, uint32_t t, PhiloxKey key)
+{
+    const uint4 w = philox4x32_10((uint32_t)cell >> 3, t, kStreamFlip, 0u, key);
+    return (word_of(w, ((uint32_t)cell >> 1) & 3u) >> (16 * (cell & 1))) & 0xFFFFu;
+}
 
 // Forest entries are read and written with relaxed workgroup-scope atomics,
 // which the caches may serve stale within a launch (agent-scope loads would
@@ -272,19 +290,26 @@ __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
     }
 }
 
-// Encoded canonical index of the cluster of local root x (after the unite
-// pass): the walk stops at the tree root, whose index is the cluster's
-// smallest site, or at the first encoding the store pass has already
-// written on the way.
-__device__ __forceinline__ int encoded_canon(const int32_t *lab, int x)
+// Tree root of local root x after the unite pass, or the first encoding the
+// store pass has already written on the way (a negative value).  The tree
+// root's index is the cluster's smallest site.
+__device__ __forceinline__ int root_or_encoding(const int32_t *lab, int x)
 {
     for (int it = 0; it < kWalkCap; ++it) {
         const int v = lab_load(lab, x);
-        if (v < 0) return v;
-        if (v == x) return kCanonBase + x;
+        if (v < 0 || v == x) return v;
         x = v & kIdxMask;
     }
-    return kCanonBase + x;
+    return x;
+}
+
+// Encoding stored for the cluster of local root x in sweep t: its smallest
+// site and its flip coin.
+__device__ __forceinline__ int canon_encoding(const int32_t *lab, int x, uint32_t t, PhiloxKey key)
+{
+    const int v = root_or_encoding(lab, x);
+    if (v < 0) return v;
+    return kCanonBase + v + (int)(cluster_coin(v, t, key) << 30);
 }
 
 // Canonical label (smallest site index of the cluster) of any site once the
@@ -293,12 +318,51 @@ __device__ __forceinline__ int encoded_canon(const int32_t *lab, int x)
 __device__ __forceinline__ int canonical_label(const int32_t *label, int64_t i)
 {
     const int v = label[i];
-    if (v < 0) return v - kCanonBase;
+    if (v < 0) return v & kIdxMask;
     const int r = (v & kTag) ? (int)i : v;
     const int w = label[r];
-    if (w < 0) return w - kCanonBase;
-    if (w & kTag) return encoded_canon(label, r) - kCanonBase;
+    if (w < 0) return w & kIdxMask;
+    if (w & kTag) {
+        const int e = root_or_encoding(label, r);
+        return e < 0 ? (e & kIdxMask) : e;
+    }
     return r;
+}
+
+// Flip mask (bit k = site k) of the cell of a flip kernel's thread, from the
+// labels of its 16 sites (lab), the tile's labels staged in LDS (LAB, laid
+// out by lds_pos) and the coins of the tile's own sites (CB, one 16-bit word
+// per cell).  A site's label is its tile-local root r; r's entry holds the
+// stored encoding (canonical site and coin) when r's cluster leaves the tile,
+// else r itself, whose coin is the tile's.  Only LDS is read.
+template <int NC, int TX, int TY, int TZ>
+__device__ __forceinline__ uint32_t cell_flip_mask(const int (&lab)[16], const int *LAB, const uint32_t *CB,
+                                                  const TileIdx<TX, TY, TZ> &ti, uint32_t t, PhiloxKey key)
+{
+    int last_in = -1;
+    uint32_t last_coin = 0, mask = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int r0 = lab[k];  // tile-local root, or an encoding (the site is a merged local root)
+        uint32_t coin;
+        if (r0 < 0) {
+            coin = ((uint32_t)r0 >> 30) & 1u;
+        } else if (r0 & kTag) {
+            coin = cluster_coin(r0 & kIdxMask, t, key);  // not produced by a complete sweep; kept in range
+        } else if (r0 == last_in) {
+            coin = last_coin;
+        } else {
+            const int key16 = ti.local_key(r0);
+            const int v = LAB[lds_pos<NC>(key16)];
+            if (v < 0) coin = ((uint32_t)v >> 30) & 1u;
+            else if (v & kTag) coin = cluster_coin(v & kIdxMask, t, key);  // as above
+            else coin = (CB[key16 >> 4] >> (key16 & 15)) & 1u;
+            last_in = r0;
+            last_coin = coin;
+        }
+        mask |= coin << k;
+    }
+    return mask;
 }
 
 // Site `site` of the neighbour cell `code` (lattice.hpp codes) of the cell
@@ -586,8 +650,9 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 // tile (two launches, the second seeing the first complete):
 //   kPassUnite  unite the local roots of the two names of every pair;
 //   kPassStore  store the encoded root of its tree (the cluster's smallest
-//               site) in every local root of the list (walks stop at the
-//               first stored encoding, so they shorten as the pass proceeds).
+//               site and its flip coin) in every local root of the list
+//               (walks stop at the first stored encoding, so they shorten as
+//               the pass proceeds).
 enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 
 // Unite pass of one tile (kBlock threads).  The pairs of a tile mostly share
@@ -724,7 +789,8 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
     constexpr int H = kTileRoots;
     __shared__ int HK[PASS == kPassUnite ? 1 : H];
     const int rep = c.tile_rep[blockIdx.x];
-    if (c.state[rep]->remaining <= 0) return;
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
     int *head = d.pairs + (int64_t)tile * d.list_stride;
@@ -745,7 +811,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
         for (int k = tid; k < m; k += kForestThreads) {
             if (rp[k] != k) continue;
             const int r = head[2 + k];
-            const int e = encoded_canon(lab, r);
+            const int e = canon_encoding(lab, r, st.t, d.key);
             HK[k] = e;
             lab_store(lab, r, e);
         }
@@ -757,7 +823,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
     if (nroots > 0) {
         for (int k = tid; k < nroots; k += kForestThreads) {
             const int r = head[2 + k];
-            lab_store(lab, r, encoded_canon(lab, r));
+            lab_store(lab, r, canon_encoding(lab, r, st.t, d.key));
         }
         return;
     }
@@ -774,7 +840,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
             if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
             if (prev == -1 || prev == key) return;
         }
-        lab_store(lab, key, encoded_canon(lab, key));
+        lab_store(lab, key, canon_encoding(lab, key, st.t, d.key));
     };
     for (int k = tid; k < 2 * n; k += kForestThreads) {
         const int2 p = list[k >> 1];
@@ -783,7 +849,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
     __syncthreads();
     for (int k = tid; k < H; k += kForestThreads) {
         const int key = HK[k];
-        if (key >= 0) lab_store(lab, key, encoded_canon(lab, key));
+        if (key >= 0) lab_store(lab, key, canon_encoding(lab, key, st.t, d.key));
     }
 }
 
@@ -802,7 +868,6 @@ hipError_t with_tile_shape(int shape, Args &&...args)
 
 // Launchers of the model-independent kernels (tile_common.hip).
 hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook);
-hipError_t launch_coins(const Chain &c, hipStream_t st, const LaunchHook &hook);
 
 // Per-model chain launchers (ising_tiled.hip, on_tiled.hip).
 hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook);
