@@ -371,6 +371,38 @@ int pyro_sw_graph_destroy(pyro_sw_graph *g);
 int pyro_sw_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n);
 int pyro_sw_sc_bonds(int L, int32_t *bond_a, int32_t *bond_b, int64_t n);
 
+/*
+ * For callers that cannot allocate: code under HIP graph capture, serving
+ * loops and harnesses that forbid device allocation.  Runs n_sweeps sweeps
+ * of one lattice whose spins the caller holds in device memory, as a handle
+ * made by pyro_sw_init_ext, given these spins by pyro_sw_set_spins with
+ * next_sweep = first_sweep, would run them with pyro_sw_sweep (same kernels,
+ * same tile shape, bit-identical results), and writes its records to the
+ * caller's device buffer.  No handle: nothing persists between calls.
+ *   dev_spins    device memory, int8 [N] (+1/-1; vacant sites are not
+ *                supported here) or float [n][N]; read and overwritten in
+ *                place; 16-byte aligned
+ *   L, model, T, J, seed   as in pyro_sw_init
+ *   first_sweep  global index of the first sweep (keys the random draws)
+ *   n_sweeps     in [0, 2^31 - 1]; first_sweep + n_sweeps < 2^32
+ *   dev_records  device memory for n_sweeps records of type pyro_sw_record,
+ *                80 B each, 8-byte aligned: record k describes the state after sweep
+ *                first_sweep + k
+ *   stream       HIP stream (NULL = the default stream); the call only
+ *                enqueues work and returns
+ * Workspace: a static device array of 64 MiB per device (labels, crossing
+ * lists, coins, partial sums), held until the process ends, which bounds L
+ * at 80 for every model (EINVAL beyond).  The call allocates nothing: no
+ * hipMalloc, hipFree, stream, event or graph; its first call on a device
+ * looks the array's address up.  Every call on a device shares that array,
+ * so calls whose work overlaps on one device race: serialise them (one
+ * stream, or synchronise between calls).  EINVAL for bad arguments as in
+ * pyro_sw_init, NULL or misaligned buffers, or a lattice beyond the limit;
+ * EDEVICE if a launch fails.
+ */
+int pyro_sw_sweep_static(void *dev_spins, int L, int model, double T, double J, uint64_t seed, int64_t first_sweep,
+                         int64_t n_sweeps, pyro_sw_record *dev_records, void *stream);
+
 /* Synchronise and free everything the library allocated.  NULL is a no-op. */
 int pyro_sw_destroy(pyro_sw *h);
 

@@ -939,6 +939,109 @@ int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls
     return PYRO_OK;
 }
 
+// ------------------------------------------------ no-allocation sweeps ---
+// Workspace of pyro_sw_sweep_static: one fixed array per device, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a stand-in, not a device address): each device's
+// address is looked up once with hipGetSymbolAddress and used from then on.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+int static_scratch(char **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PYRO_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PYRO_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(PYRO_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PYRO_OK;
+}
+
+// Descriptor, state and zero block map of a solo chain written into the
+// scratch by one kernel whose arguments carry them (no host buffer, no
+// memset node).
+__global__ void k_static_setup(RepDesc *desc_dst, RepDesc d, RepState **stp_dst, RepState *state, RepState s,
+                               int *map, int map_len)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *desc_dst = d;
+        *stp_dst = state;
+        *state = s;
+    }
+    for (int k = i; k < map_len; k += gridDim.x * blockDim.x) map[k] = 0;
+}
+}  // namespace
+
+int pyro_sw_sweep_static(void *dev_spins, int L, int model, double T, double J, uint64_t seed, int64_t first_sweep,
+                         int64_t n_sweeps, pyro_sw_record *dev_records, void *stream)
+{
+    int rc = check_args(L, model, T, J, PYRO_START_COLD);
+    if (rc) return rc;
+    if (!dev_spins || (n_sweeps > 0 && !dev_records)) return fail(PYRO_EINVAL, "device buffers must not be NULL");
+    if (((uintptr_t)dev_spins % 16) || ((uintptr_t)dev_records % 8))
+        return fail(PYRO_EINVAL, "spins must be 16-byte and records 8-byte aligned");
+    if (n_sweeps < 0 || n_sweeps > INT32_MAX) return fail(PYRO_EINVAL, "n_sweeps must be in [0, 2^31 - 1]");
+    if (first_sweep < 0 || first_sweep + n_sweeps > (int64_t)UINT32_MAX)
+        return fail(PYRO_EINVAL, "sweep indices must stay below 2^32");
+    const Layout ly = layout_for(L, model);
+    if (ly.total > kStaticScratchBytes)
+        return fail(PYRO_EINVAL, "lattice too large for the static workspace (64 MiB: L <= 80)");
+    if (n_sweeps == 0) return PYRO_OK;
+    char *work = nullptr;
+    rc = static_scratch(&work);
+    if (rc) return rc;
+    uint32_t thr_hi = 0, thr_lo = 0;
+    float x0 = 0.0f;
+    run_constants(T, J, &thr_hi, &thr_lo, &x0);
+    const int shape = default_tile_shape(L);
+    RepDesc d = lattice_desc(L, model, J, seed, thr_hi, thr_lo, x0, dev_spins, work, ly, nullptr, shape, 0, 0);
+    d.ring = (DevRecord *)dev_records;  // records go straight to the caller's buffer
+    d.ring_cap = (int)n_sweeps;
+    const int64_t ncell = (int64_t)L * L * L;
+    RepDesc *d_desc = (RepDesc *)(work + ly.solo_desc);
+    RepState **d_stp = (RepState **)(work + ly.solo_stp);
+    RepState *d_state = (RepState *)(work + ly.state);
+    int *map = (int *)(work + ly.solo_map);
+    const RepState s0{(uint32_t)first_sweep, (int32_t)n_sweeps, 0, -1};
+    hipStream_t st = (hipStream_t)stream;
+    k_static_setup<<<std::max(1, std::min(blocks_for(ly.map_len), 1024)), kBlock, 0, st>>>(
+        d_desc, d, d_stp, d_state, s0, map, (int)ly.map_len);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PYRO_EDEVICE, std::string("static setup: ") + hipGetErrorString(e));
+    Chain c{};
+    c.desc = d_desc;
+    c.state = d_stp;
+    c.tile_rep = c.cblk_rep = map;
+    c.nreps = 1;
+    c.shape = shape;
+    c.model = model;
+    c.ntile_blocks = (int)tiles_for(L, shape);
+    c.ncell_blocks = blocks_for(ncell);
+    const LaunchHook none{nullptr, nullptr, nullptr};
+    for (int64_t k = 0; k < n_sweeps && e == hipSuccess; ++k) e = launch_chain_sweep(c, st, none);
+    if (e == hipSuccess) e = launch_chain_energy_tail(c, st, none);
+    if (e != hipSuccess) return fail(PYRO_EDEVICE, std::string("static sweep: ") + hipGetErrorString(e));
+    return PYRO_OK;
+}
+
 int pyro_sw_destroy(pyro_sw *h)
 {
     if (!h) return PYRO_OK;

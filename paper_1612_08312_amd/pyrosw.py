@@ -47,7 +47,7 @@ EXPORTS = (
     "pyro_sw_group_destroy", "pyro_sw_group_set_slices",
     "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
     "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
-    "pyro_sw_philox_rate",
+    "pyro_sw_philox_rate", "pyro_sw_sweep_static",
     "pyro_sw_graph_init", "pyro_sw_graph_sweep", "pyro_sw_graph_moments", "pyro_sw_graph_get_spins",
     "pyro_sw_graph_set_spins", "pyro_sw_graph_get_labels", "pyro_sw_graph_set_temperature",
     "pyro_sw_graph_destroy", "pyro_sw_bonds", "pyro_sw_sc_bonds",
@@ -116,6 +116,7 @@ def load_library():
     lib.pyro_sw_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_destroy.argtypes = [vp]
     lib.pyro_sw_philox_rate.argtypes = [i64, i32, u64, P(f64), P(ctypes.c_uint32)]
+    lib.pyro_sw_sweep_static.argtypes = [vp, i32, i32, f64, f64, u64, i64, i64, vp, vp]
     lib.pyro_sw_set_tile_shape.argtypes = [vp, i32]
     lib.pyro_sw_group_create.argtypes = [P(vp), P(vp), i32, vp]
     lib.pyro_sw_group_sweep.argtypes = [vp, i64, P(i64)]
@@ -322,6 +323,16 @@ def pyro_sw_philox_rate(calls: int, repeats: int = 3, seed: int = 1):
     _check(load_library().pyro_sw_philox_rate(int(calls), int(repeats), int(seed), ctypes.byref(rate),
                                               ctypes.byref(fold)), "pyro_sw_philox_rate")
     return rate.value, fold.value
+
+
+def pyro_sw_sweep_static(dev_spins: int, L, model, T, J, seed, first_sweep, n_sweeps, dev_records: int,
+                         stream=None):
+    """Enqueue n_sweeps sweeps of the lattice whose spins are at device
+    address dev_spins, records to device address dev_records (80 B each),
+    using the library's static workspace (no allocation)."""
+    _check(load_library().pyro_sw_sweep_static(int(dev_spins), int(L), int(model), float(T), float(J), int(seed),
+                                               int(first_sweep), int(n_sweeps), int(dev_records),
+                                               _stream_ptr(stream)), "pyro_sw_sweep_static")
 
 
 def pyro_sw_destroy(h):
