@@ -6,7 +6,9 @@ Workload: Ising model on the periodic pyrochlore lattice, L = 128
 lattices resident at T = 4.205, 4.210, 4.2139, 4.218, 4.223 (seeds 1..5,
 random start).  One step = one Swendsen-Wang sweep of each of the five
 lattices (bond activation, cluster labeling, cluster flips, moments);
---steps 10000 is the full five-temperature run.
+--steps 10000 --warmup 0 is the full five-temperature run (sweeps 1..10^4
+from the random start, Binder U per temperature over sweeps 5001..10^4 and
+over all sweeps).
 
 Printed on one JSON line: spin-updates/s over the timed steps, the roofline
 of the dominant kernel (algorithmic bytes per launch / its mean duration,
@@ -42,6 +44,7 @@ def bytes_per_site(shape):
         "unite": 0.0,                  # forest walks over the crossing lists (data dependent)
         "canon_store": 0.0,            # idem
         "flip": 4.0 + 1.0 + 1.0,       # read labels, read and write spins (coins are drawn in the kernel)
+        "persist": 11.0,               # the whole sweep (every pass), per sweep of each lattice
         "energy": 1.0,                 # read spins
         "finalize": 0.0,
     }
@@ -147,6 +150,40 @@ def copy_peak_gbs(dev, mib=1024, reps=5):
     return 2 * (mib << 20) / (best * 1e-3) / 1e9
 
 
+def batch_modes(sweeps, stream, dev):
+    """The 96-replica batch under each Ising mode of a group (per-sweep
+    graphs; persistent fused launch; each with and without LDS-resident
+    small lattices), autotuned tile shape: spin-updates/s of each, `sweeps`
+    sweeps after 5 warm-up sweeps."""
+    import torch
+
+    from paper_1612_08312_amd import pyrosw, workloads
+
+    specs = workloads.batch_replicas()
+    lats = [pyrosw.Lattice(L=r["L"], model=r["model"], T=r["T"], J=r["J"], seed=r["seed"], start=r["start"],
+                           device=dev, stream=stream) for r in specs]
+    sites = sum(lt.N for lt in lats)
+    group = pyrosw.Group(lats, stream)
+    shape = group.autotune(trial_sweeps=3)[0]
+    out = {"tile_shape": pyrosw.TILE_SHAPES[shape]}
+    for name, mode, res in (("graph", pyrosw.PYRO_MODE_GRAPH, False), ("graph_resident", pyrosw.PYRO_MODE_GRAPH, True),
+                            ("persistent", pyrosw.PYRO_MODE_PERSISTENT, False),
+                            ("persistent_resident", pyrosw.PYRO_MODE_PERSISTENT, True)):
+        group.set_mode(mode, res)
+        group.sweep(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        group.sweep(sweeps)
+        torch.cuda.synchronize()
+        out[name] = sites * sweeps / (time.perf_counter() - t0)
+        for lt in lats:
+            lt.moments()
+    group.close()
+    for lt in lats:
+        lt.close()
+    return out
+
+
 def batched_vs_plain(sweeps, stream, dev):
     """The 96-replica batch (L in {8,12,16,24,32,48} x 16 temperatures in
     [4.19, 4.24]) swept `sweeps` times as one group (one captured graph per
@@ -168,6 +205,7 @@ def batched_vs_plain(sweeps, stream, dev):
     sites = sum(lt.N for lt in lats)
     group = pyrosw.Group(lats, stream)
     shape = pyrosw.TILE_SHAPES[group.autotune(trial_sweeps=3)[0]]
+    mode, resident = group.mode()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     group.sweep(sweeps)
@@ -195,6 +233,8 @@ def batched_vs_plain(sweeps, stream, dev):
         "sites_per_sweep": sites,
         "sweeps": sweeps,
         "tile_shape": shape,
+        "ising_mode": "persistent" if mode == pyrosw.PYRO_MODE_PERSISTENT else "graph",
+        "lds_resident_small_lattices": bool(resident),
         "batched_spin_updates_per_s": sites * sweeps / t_batched,
         "plain_spin_updates_per_s": sites * sweeps / t_plain,
         "speedup": t_plain / t_batched,
@@ -377,9 +417,11 @@ def main():
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--cpu-sweeps", type=int, default=4, help="oracle sweeps for cpu_baseline (0: skip)")
     ap.add_argument("--tile-shape", type=int, default=-1, help="tile shape id (-1: autotune)")
+    ap.add_argument("--ising-mode", choices=("auto", "graph", "persistent"), default="auto",
+                    help="Ising sweep mode of the group (auto: the autotuner's choice)")
     ap.add_argument("--batch-sweeps", type=int, default=2000,
                     help="sweeps of the 96-replica batched-vs-plain comparison (0: skip)")
-    ap.add_argument("--serve-jobs", type=int, default=16,
+    ap.add_argument("--serve-jobs", type=int, default=100,
                     help="jobs of the Poisson serving stream for the served-vs-plain comparison (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the job server")
     ap.add_argument("--serve-quantum-ms", type=float, default=20.0, help="lane quantum of the job server")
@@ -388,6 +430,8 @@ def main():
                     help="sweeps of the generic graph-path leg (simple cubic L=256, pyrochlore L=128; 0: skip)")
     ap.add_argument("--diluted-sweeps", type=int, default=500,
                     help="sweeps of the site-diluted Ising L=128 leg and its pure twin (0: skip)")
+    ap.add_argument("--batch-modes-sweeps", type=int, default=0,
+                    help="sweeps of the 96-replica batch timed under each Ising mode (0: skip)")
     ap.add_argument("--pmc-probe", action="store_true", help="run the counter-collection workload and exit")
     ap.add_argument("--roofline-steps", type=int, default=200,
                     help="steps of the pass that times the dominant kernel with HIP events")
@@ -417,26 +461,21 @@ def main():
             for T, s in zip(temps, seeds)]
     N = lats[0].N
     group = pyrosw.Group(lats, stream)
-    if args.tile_shape >= 0:
-        group.set_tile_shape(1, args.tile_shape)
-        shape = pyrosw.TILE_SHAPES[args.tile_shape]
+    if args.tile_shape >= 0 or args.ising_mode != "auto":
+        tshape = args.tile_shape if args.tile_shape >= 0 else pyrosw.PYRO_TILE_8x8x8
+        group.set_tile_shape(1, tshape)
+        shape = pyrosw.TILE_SHAPES[tshape]
+        if args.ising_mode != "auto":
+            group.set_mode(pyrosw.PYRO_MODE_PERSISTENT if args.ising_mode == "persistent" else pyrosw.PYRO_MODE_GRAPH)
     else:
         shapes = group.autotune(trial_sweeps=3)
         shape = pyrosw.TILE_SHAPES[shapes[0]]
         log("bench: autotuned tile shape", shape)
+    ising_mode = "persistent" if group.mode()[0] == pyrosw.PYRO_MODE_PERSISTENT else "graph"
+    log("bench: Ising mode", ising_mode)
     byte_model = bytes_per_site(shape)
 
-    # Find the dominant kernel over a few timed sweeps (events on every kernel).
-    pyrosw.pyro_sw_group_set_timing(group.g, -1)
-    group.sweep(max(1, min(args.warmup, 5)))
-    kt = {k: list(v) for k, v in pyrosw.pyro_sw_group_kernel_times(group.g).items()}
-    names = list(kt)
-    dominant = max(kt, key=lambda k: kt[k][1])
-    log("bench: mean us per launch over probe sweeps:",
-        {k: round(v[1] / v[0] * 1e3, 1) for k, v in kt.items() if v[0]})
-
-    # Warmup, then the timed region with HIP events on the dominant kernel only.
-    pyrosw.pyro_sw_group_set_timing(group.g, 0)
+    # Warmup, then the timed region.
     group.sweep(args.warmup)
     for lt in lats:
         lt.moments()  # discard warmup records
@@ -447,6 +486,20 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     recs = [lt.moments() for lt in lats]
+    # Per-pass breakdown (HIP events on every kernel of per-sweep launches,
+    # three sweeps), then the dominant kernel of the timed mode: the
+    # persistent launch itself, or the slowest pass.
+    saved_mode = group.mode()
+    group.set_mode(pyrosw.PYRO_MODE_GRAPH, saved_mode[1])
+    pyrosw.pyro_sw_group_set_timing(group.g, -1)
+    group.sweep(10)
+    kt = {k: list(v) for k, v in pyrosw.pyro_sw_group_kernel_times(group.g).items()}
+    pyrosw.pyro_sw_group_set_timing(group.g, 0)
+    group.set_mode(*saved_mode)
+    names = list(kt)
+    dominant = "persist" if ising_mode == "persistent" else max(kt, key=lambda k: kt[k][1])
+    log("bench: mean us per launch over probe sweeps:",
+        {k: round(v[1] / v[0] * 1e3, 1) for k, v in kt.items() if v[0]})
     # Mean duration of the dominant kernel: HIP events around each of its
     # launches on the group's stream (direct launches instead of the graph).
     roof_steps = max(1, min(args.steps, args.roofline_steps))
@@ -476,11 +529,12 @@ def main():
     fp, tbytes = MEASURED_TRAFFIC.get(dominant, (None, None))
     if fp == kernel_fingerprint() and launches_per_step == len(lats):
         traffic = tbytes
-    binder = {}
+    binder, binder_all = {}, {}
     for T, r in zip(temps, recs):
         half = r[len(r) // 2:]
         if len(half):
             binder[str(T)] = float(np.mean(half["m4"]) / np.mean(half["m2"]) ** 2)
+            binder_all[str(T)] = float(np.mean(r["m4"]) / np.mean(r["m2"]) ** 2)
     out = {
         "metric": METRIC,
         "value": value,
@@ -505,6 +559,7 @@ def main():
             "sweeps_per_lattice": args.steps,
             "step": "one SW sweep of each lattice (one captured graph per lattice, run concurrently)",
             "tile_shape": shape,
+            "ising_mode": ising_mode,
         },
         "roofline": {
             "bound": "hbm",
@@ -530,6 +585,7 @@ def main():
         },
         "sweep_alg_roofline_frac": value * SWEEP_BYTES_PER_SITE / (HBM_PEAK_GBS * 1e9),
         "binder_U_second_half": binder,
+        "binder_U_all_sweeps": binder_all,
         "kernel_mean_us_probe": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},
     }
     if args.on_sweeps > 0:
@@ -541,6 +597,9 @@ def main():
     if args.graph_sweeps > 0:
         log(f"bench: generic graph path, {args.graph_sweeps} sweeps per lattice")
         out["graph"] = graph_throughput(args.graph_sweeps, stream, dev)
+    if args.batch_modes_sweeps > 0:
+        log(f"bench: 96-replica batch under each Ising mode, {args.batch_modes_sweeps} sweeps")
+        out["batch_modes"] = batch_modes(args.batch_modes_sweeps, stream, dev)
     if args.batch_sweeps > 0:
         log(f"bench: 96-replica batch, {args.batch_sweeps} sweeps, batched then plain")
         out["batched"] = batched_vs_plain(args.batch_sweeps, stream, dev)

@@ -214,17 +214,38 @@ int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, doub
  *                          another (members are dealt largest first to the
  *                          lightest slice; default min(n, 8)).  Changes speed
  *                          only, never results.
+ *   pyro_sw_group_set_mode how the Ising members are swept (the O(n)
+ *                          members always use per-sweep graphs):
+ *                          ising_mode PYRO_MODE_GRAPH: one captured graph of
+ *                          the sweep's kernels per sweep (the default);
+ *                          PYRO_MODE_PERSISTENT: every sweep of a call in one
+ *                          persistent fused launch per slice (captured as a
+ *                          graph), whose workgroups take (replica, phase,
+ *                          tile) items so that the passes of different
+ *                          replicas overlap.  resident != 0: Ising members of
+ *                          L <= 16 without vacant sites run LDS-resident, one
+ *                          workgroup per lattice holding it whole for every
+ *                          sweep of a call, beside the slices.  Modes change
+ *                          speed only, never results.
+ *   pyro_sw_group_get_mode the current modes (either output may be NULL).
+ *   pyro_sw_group_autotune also chooses the Ising modes (every combination
+ *                          of mode and tile shape that applies is timed).
  *   pyro_sw_group_set_timing / pyro_sw_group_kernel_times  as for a handle.
  *   pyro_sw_group_destroy  frees the group only (NULL is a no-op).
  * Errors: PYRO_EINVAL (arguments), PYRO_ESTATE (a member failed or is busy),
- * PYRO_ENOMEM, PYRO_EDEVICE.
+ * PYRO_ENOMEM, PYRO_EDEVICE (also when a persistent launch gave up a wait:
+ * reported by the next pyro_sw_moments of a member, whose device state then
+ * disagrees with the host's).
  */
 typedef struct pyro_sw_group pyro_sw_group;
+enum { PYRO_MODE_GRAPH = 0, PYRO_MODE_PERSISTENT = 1 };
 int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, void *stream);
 int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_member);
 int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out);
 int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape);
 int pyro_sw_group_set_slices(pyro_sw_group *g, int nslices);
+int pyro_sw_group_set_mode(pyro_sw_group *g, int ising_mode, int resident);
+int pyro_sw_group_get_mode(const pyro_sw_group *g, int *ising_mode, int *resident);
 int pyro_sw_group_set_timing(pyro_sw_group *g, int kernel_mask);
 int pyro_sw_group_kernel_times(pyro_sw_group *g, const char **names, int64_t *launches, double *ms,
                                int cap, int *n_out);
@@ -325,6 +346,26 @@ int pyro_sw_server_destroy(pyro_sw_server *s);
  * EINVAL for calls outside [1, 2^32], repeats < 1 or NULL outputs.
  */
 int pyro_sw_philox_rate(int64_t calls, int repeats, uint64_t seed, double *calls_per_second, uint32_t *fold);
+
+/*
+ * Measurement helper, not part of a sweep: device atomic throughput on the
+ * current device, the ceiling of the global merge (a hook is a load and a
+ * compare-and-swap of a label entry) and of work counters.
+ *   mode 0   `ops` operations, each a load and a compare-and-swap from the
+ *            loaded value v to v + 1 of a pseudo-random word of a zeroed
+ *            array of `words` 32-bit words (a label array has one per site)
+ *   mode 1   `ops` atomic adds of 1 to one word
+ *   ops_per_second  operations per second of the fastest of `repeats`
+ *                   launches (HIP events around the launch)
+ *   succeeded  swaps that took effect (mode 0; ops in mode 1), and
+ *   word_sum   the sum of the array after the last launch: equal to
+ *              succeeded when no update was lost
+ * Synchronous; allocates and frees the array, two counters and a stream.
+ * EINVAL for a mode other than 0 or 1, words outside [1, 2^32], ops outside
+ * [1, 2^40], repeats < 1 or NULL outputs.
+ */
+int pyro_sw_atomic_rate(int mode, int64_t words, int64_t ops, int repeats, double *ops_per_second,
+                        int64_t *succeeded, int64_t *word_sum);
 
 /*
  * Generic lattices: the same Swendsen-Wang sweep on any graph supplied as a

@@ -16,8 +16,8 @@ CSRC = os.path.join(_HERE, "csrc")
 BUILD = os.path.join(_HERE, "_build")
 LIB = os.path.join(_HERE, "libpyrosw.so")
 
-SOURCES = ["init.hip", "tile_common.hip", "ising_tiled.hip", "on_tiled.hip", "pyro_sw.hip", "server.hip",
-           "graph.hip"]
+SOURCES = ["init.hip", "tile_common.hip", "ising_tiled.hip", "on_tiled.hip", "resident.hip", "pyro_sw.hip",
+           "server.hip", "graph.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

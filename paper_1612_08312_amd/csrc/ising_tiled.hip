@@ -34,24 +34,33 @@
 
 namespace pyro {
 
+// LDS of the tile pass and of the flip pass of one tile.
 template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
+struct IsingTileLds {
+    uint32_t P[kForestSlots<TX * TY * TZ>];     // tile forest
+    uint32_t SM[TX * TY * TZ];                  // spin masks of the cells
+    uint32_t U[kUnionsPerCell * TX * TY * TZ];  // union list
+    uint8_t K4[64];
+    int64_t red[16];
+};
+
+template <int TX, int TY, int TZ>
+struct IsingFlipLds {
+    int LAB[16 * TX * TY * TZ];  // labels of the tile's sites
+    uint32_t CB[TX * TY * TZ];   // coins of the tile's sites
+    int64_t red[16];
+};
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void ising_tile_pass(const RepDesc &d, const RepState &st, int tile, int tid,
+                                                IsingTileLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
-    __shared__ uint32_t P[kForestSlots<NC>];
-    __shared__ uint32_t SM[NC];
-    __shared__ uint32_t U[kUnionsPerCell * NC];
-    __shared__ uint8_t K4[64];
-    __shared__ int64_t red[16];
-
-    const int rep = c.tile_rep[blockIdx.x];
-    const RepState st = *c.state[rep];
-    if (st.remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
+    uint32_t *P = S.P, *SM = S.SM, *U = S.U;
+    uint8_t *K4 = S.K4;
+    int64_t *red = S.red;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
     const int8_t *__restrict__ s = (const int8_t *)d.spins;
-    const int tid = threadIdx.x;
     const int L = d.L;
     const int lcid = tid;  // local cell of the thread
     const int lx = lcid % TX, ly = (lcid / TX) % TY, lz = lcid / (TX * TY);
@@ -106,24 +115,30 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     if (tid == 0) d.ipart[tile] = bsum;
 }
 
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
+{
+    __shared__ IsingTileLds<TX, TY, TZ> S;
+    const int rep = c.tile_rep[blockIdx.x];
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    ising_tile_pass<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+}
+
 // One workgroup per tile: the labels of the tile's sites and the coins of
 // its own clusters are staged in LDS, so the coin of every site's cluster
 // (site -> local root -> stored encoding or the root's own coin) costs no
 // scattered global read; then flips and the magnetisation of the new state.
 template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
+__device__ __forceinline__ void ising_flip_pass(const RepDesc &d, const RepState &st, int tile, int tid,
+                                                IsingFlipLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
-    __shared__ int LAB[16 * NC];
-    __shared__ uint32_t CB[NC];
-    __shared__ int64_t red[16];
-    const int rep = c.tile_rep[blockIdx.x];
-    const RepState st = *c.state[rep];
-    if (st.remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
+    int *LAB = S.LAB;
+    uint32_t *CB = S.CB;
+    int64_t *red = S.red;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
-    const int tid = threadIdx.x;
     const int L = d.L;
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
@@ -171,24 +186,33 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
     if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
 }
 
-// Records and state: energy partials (state before this sweep) into the
-// pending record, magnetisation of the new state into a new record.
-__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_ising(Chain c)
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
 {
-    __shared__ int64_t red[16];
-    const int rep = blockIdx.x;
+    __shared__ IsingFlipLds<TX, TY, TZ> S;
+    const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
+    ising_flip_pass<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+}
+
+// Records and state: energy partials (state before this sweep) into the
+// pending record, magnetisation of the new state into a new record (a block
+// of NT threads; the sums are exact integers).
+template <int NT>
+__device__ __forceinline__ void ising_finalize(const RepDesc &d, const RepState &st, RepState *stp, int tid,
+                                               int64_t *red)
+{
     const int ntiles = d.ntx * d.nty * d.ntz;
     int64_t E = 0, M = 0;
-    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) {
+    for (int k = tid; k < ntiles; k += NT) {
         E += d.ipart[k];
         M += d.ipart[d.mpart_off + k];
     }
     E = block_sum<int64_t>(E, red);
     M = block_sum<int64_t>(M, red);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         if (st.e_pending >= 0) {
             d.ring[st.e_pending].bond_sum = E;
             d.ring[st.e_pending].E = -d.J * (double)E;
@@ -214,8 +238,17 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize_ising(Chain c)
         ns.remaining = st.remaining - 1;
         ns.ring_used = slot + 1;
         ns.e_pending = slot < d.ring_cap ? slot : -1;
-        *c.state[rep] = ns;
+        *stp = ns;
     }
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_ising(Chain c)
+{
+    __shared__ int64_t red[16];
+    const int rep = blockIdx.x;
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    ising_finalize<kFinalizeThreads>(c.desc[rep], st, c.state[rep], threadIdx.x, red);
 }
 
 // Energy of the current state for replicas whose last record is pending.
@@ -300,6 +333,177 @@ hipError_t launch_ising_energy_tail(const Chain &c, hipStream_t st, const Launch
     PYRO_LAUNCH(kKEnergy, k_energy_ising, c.ncell_blocks, kBlock, c);
     PYRO_LAUNCH(kKFinalize, k_energy_tail_finalize_ising, c.nreps, kBlock, c);
     return hipSuccess;
+}
+
+// ------------------------------------------------ persistent fused sweep ---
+// All sweeps of a call for every replica of an Ising chain in one launch:
+// a fixed grid of workgroups takes work items, each one phase of one tile of
+// one replica (tile pass, unite, store, flip; the last flip item of a sweep
+// also finalises the record), until no item is left.  Items of a replica
+// are numbered k = (4 s + phase) T + tile (T tiles, sweep s of the call) and
+// handed out in that order by the replica's cursor, so an item depends only
+// on items handed out before it: it waits until the replica's completed-item
+// count reaches 4 s T + phase T (the previous phase complete), which is
+// deadlock-free whatever the number of resident workgroups, since every
+// item handed out is held by a running workgroup.  A workgroup prefers a
+// replica whose next phase is ready, so replicas drift apart and the
+// issue-bound passes (tile, flip) of some run beside the latency-bound
+// passes (unite, store) of others on the same compute units.
+//
+// Visibility between phases: after an item its writes are released to agent
+// scope (L2 written back) before the completed count is raised; a waiting
+// item acquires at agent scope (caches invalidated) after the count is
+// reached.  Every wait is bounded: past kPersistSpin polls the error flag is
+// raised and every workgroup leaves (the host reports the error).
+//
+// Control words (ints, one 128-byte line per replica; cleared by
+// k_persist_reset before each launch): ctl[0] error flag; for replica r at
+// kPersistStride (r + 1): cursor, done, flips arrived this sweep, sweeps of
+// the call, items of the call.
+__device__ __forceinline__ int *persist_ctl(int *ctl, int r) { return ctl + kPersistStride * (r + 1); }
+
+__global__ void k_persist_reset(Chain c, int *ctl)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) ctl[0] = 0;
+    if (r >= c.nreps) return;
+    const RepDesc &d = c.desc[r];
+    const int S = max(c.state[r]->remaining, 0);
+    int *q = persist_ctl(ctl, r);
+    q[0] = 0;
+    q[1] = 0;
+    q[2] = 0;
+    q[3] = S;
+    q[4] = 4 * S * d.ntx * d.nty * d.ntz;
+}
+
+__device__ __forceinline__ int ld_agent(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_persist_ising(Chain c, int *ctl)
+{
+    constexpr int NC = TX * TY * TZ;
+    __shared__ union {
+        IsingTileLds<TX, TY, TZ> tile;
+        UniteLds unite;
+        int HK[kTileRoots];
+        IsingFlipLds<TX, TY, TZ> flip;
+        int64_t red[16];
+    } S;
+    __shared__ int take[3];  // replica (-1: nothing left), item, last flip of the sweep
+    const int R = c.nreps;
+    int next = blockIdx.x % R;  // replica to try first (thread 0)
+    for (;;) {
+        // The thread index is laundered on every item, so that nothing derived
+        // from it is hoisted out of the item loop: each item is independent,
+        // and values kept live across items would only raise register
+        // pressure (occupancy).
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        if (tid == 0) {
+            int r_take = -1, k = 0;
+            // a replica whose next item is ready, among the next few
+            for (int probe = 0; probe < 4 && probe < R && r_take < 0; ++probe) {
+                const int r = (next + probe) % R;
+                int *q = persist_ctl(ctl, r);
+                const int total = q[4], T = total / max(4 * q[3], 1);
+                const int cur = ld_agent(&q[0]);
+                if (cur >= total || ld_agent(&q[1]) < (cur / T) * T) continue;
+                k = atomicAdd(&q[0], 1);
+                if (k < total) r_take = r;
+            }
+            // otherwise any replica with items left (the item may wait)
+            for (int probe = 0; probe < R && r_take < 0; ++probe) {
+                const int r = (next + probe) % R;
+                int *q = persist_ctl(ctl, r);
+                if (ld_agent(&q[0]) >= q[4]) continue;
+                k = atomicAdd(&q[0], 1);
+                if (k < q[4]) r_take = r;
+            }
+            if (ld_agent(&ctl[0])) r_take = -1;
+            take[0] = r_take;
+            take[1] = k;
+            if (r_take >= 0) {
+                next = (r_take + 1) % R;
+                // wait for the previous phase of this replica
+                int *q = persist_ctl(ctl, r_take);
+                const int T = q[4] / (4 * q[3]);
+                const int need = (k / T) * T;
+                for (int spin = 0; ld_agent(&q[1]) < need; ++spin) {
+                    if (spin >= kPersistSpin || ld_agent(&ctl[0])) {
+                        atomicOr(&ctl[0], 1);
+                        take[0] = -1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+        __syncthreads();
+        // the item is the same for every lane: keep it in scalar registers
+        const int r = __builtin_amdgcn_readfirstlane(take[0]), k = __builtin_amdgcn_readfirstlane(take[1]);
+        if (r < 0) return;
+        const RepDesc &d = c.desc[r];
+        const int T = d.ntx * d.nty * d.ntz;
+        const int seg = k / T, tile = k - seg * T, phase = seg & 3;
+        const RepState st = *c.state[r];
+        if (phase == 0) ising_tile_pass<TX, TY, TZ>(d, st, tile, tid, S.tile);
+        else if (phase == 1) unite_tile<NC>(d, tile, tid, S.unite);
+        else if (phase == 2) store_tile<NC>(d, st, tile, tid, S.HK);
+        else ising_flip_pass<TX, TY, TZ>(d, st, tile, tid, S.flip);
+        __syncthreads();
+        int *q = persist_ctl(ctl, r);
+        if (phase == 3) {
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const int old = atomicAdd(&q[2], 1);
+                take[2] = (old + 1) % T == 0;
+                if (take[2]) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(take[2])) ising_finalize<NC>(d, st, c.state[r], tid, S.red);
+            __syncthreads();
+        }
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicAdd(&q[1], 1);
+        }
+    }
+}
+
+struct IsingPersist {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(const Chain &c, int *ctl, int grid, hipStream_t st, const LaunchHook &hook)
+    {
+        k_persist_reset<<<blocks_for(c.nreps), kBlock, 0, st>>>(c, ctl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        PYRO_LAUNCH(kKPersist, (k_persist_ising<TX, TY, TZ>), grid, TX * TY * TZ, c, ctl);
+        return hipSuccess;
+    }
+    template <int TX, int TY, int TZ>
+    static hipError_t grid(int *blocks_per_cu)
+    {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_persist_ising<TX, TY, TZ>,
+                                                            TX * TY * TZ, 0);
+    }
+};
+
+struct IsingPersistGrid {
+    template <int TX, int TY, int TZ>
+    static hipError_t run(int *blocks_per_cu) { return IsingPersist::grid<TX, TY, TZ>(blocks_per_cu); }
+};
+
+hipError_t launch_ising_persistent(const Chain &c, int *ctl, int grid, hipStream_t st, const LaunchHook &hook)
+{
+    if (c.nreps == 0) return hipSuccess;
+    return with_tile_shape<IsingPersist>(c.shape, c, ctl, grid, st, hook);
+}
+
+hipError_t ising_persistent_blocks_per_cu(int shape, int *blocks_per_cu)
+{
+    return with_tile_shape<IsingPersistGrid>(shape, blocks_per_cu);
 }
 
 }  // namespace pyro

@@ -101,6 +101,8 @@ enum KernelId : int {
     kKFinalize,
     kKAxis,      // O(n) axis
     kKCompress,  // forest store pass ("canon_store")
+    kKPersist,   // persistent fused sweep (all sweeps of a call)
+    kKResident,  // LDS-resident small lattices (all sweeps of a call)
     kNumKernels
 };
 const char *kernel_name(int id);
@@ -120,6 +122,14 @@ hipError_t launch_chain_sweep(const Chain &c, hipStream_t st, const LaunchHook &
 // Energy of the current state into the pending record of every replica of
 // the chain, then mark it complete.
 hipError_t launch_chain_energy_tail(const Chain &c, hipStream_t st, const LaunchHook &hook);
+// Persistent fused Ising sweep: every sweep of a call for all replicas of the
+// chain in one launch of `grid` workgroups (control words: kPersistStride
+// ints per replica plus one line; see ising_tiled.hip).
+constexpr int kPersistStride = 32;
+constexpr int kPersistSpin = 1 << 22;  // polls of a wait (about 1 us each) before the launch gives up
+hipError_t launch_ising_persistent(const Chain &c, int *ctl, int grid, hipStream_t st, const LaunchHook &hook);
+hipError_t ising_persistent_blocks_per_cu(int shape, int *blocks_per_cu);
+
 // Canonical label (smallest site index of the cluster) of every site of one
 // replica into the device array out[N].
 hipError_t launch_canonical_labels(const RepDesc &d, int32_t *out, hipStream_t st);

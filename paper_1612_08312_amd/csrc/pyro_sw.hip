@@ -23,6 +23,7 @@
 #include "../../include/pyro_sw.h"
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "resident.hpp"
 
 using namespace pyro;
 
@@ -59,6 +60,47 @@ __global__ __launch_bounds__(256) void k_philox_rate(uint64_t calls, PhiloxKey k
     if ((threadIdx.x & 63) == 0) wf[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) out[blockIdx.x] = wf[0] ^ wf[1] ^ wf[2] ^ wf[3];
+}
+
+// Device atomic throughput probe.  Mode 0: every op loads a pseudo-random
+// word of a[0 .. words) and compare-and-swaps it from the loaded value v to
+// v + 1, as a forest hook does; each block adds its successful swaps to
+// out[0], so that sum(a) = out[0] checks that no swap was lost.  Mode 1:
+// every op adds 1 to a[0] (one address, as a work counter).
+__global__ __launch_bounds__(256) void k_atomic_rate(int mode, uint32_t *a, uint64_t words, uint64_t ops,
+                                                     unsigned long long *out)
+{
+    __shared__ unsigned long long ws[4];
+    unsigned long long ok = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ops; i += stride) {
+        if (mode == 0) {
+            uint64_t h = (i + 1) * 0x9E3779B97F4A7C15ull;
+            h ^= h >> 29;
+            const uint64_t w = h % words;
+            const uint32_t v = __hip_atomic_load(a + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok += atomicCAS(a + w, v, v + 1u) == v;
+        } else {
+            atomicAdd(a, 1u);
+            ++ok;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) ok += __shfl_xor(ok, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = ok;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, ws[0] + ws[1] + ws[2] + ws[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sum_words(const uint32_t *a, uint64_t words, unsigned long long *out)
+{
+    __shared__ unsigned long long ws[4];
+    unsigned long long v = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        v += a[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, ws[0] + ws[1] + ws[2] + ws[3]);
 }
 
 // Default tile shape for lattices of edge up to L (measured on MI355X):
@@ -215,14 +257,21 @@ struct ChainTables {
     RepState **d_stp = nullptr;
     int *d_tile_rep = nullptr, *d_cblk_rep = nullptr;
     Chain chain{};
+    int *d_ctl = nullptr;    // control words of a persistent launch (groups in persistent mode)
+    int persist_grid = 0;    // workgroups of that launch
     bool owned = true;       // tables in `block` (groups) or in a workspace (solo)
     void *block = nullptr;   // stream-ordered allocation holding a group's tables
     hipStream_t stream = nullptr;
 };
 
 // Process-wide autotuning results: (model, multiset of L) -> tile shape.
+struct TuneChoice {
+    int shape;
+    int ising_mode;  // Ising chains only
+    bool resident;
+};
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_cache;
+std::map<std::string, TuneChoice> g_tune_cache;
 
 }  // namespace
 
@@ -262,7 +311,8 @@ struct pyro_sw {
 // latency-bound passes of one slice overlap the arithmetic of another.
 struct SubGroup {
     ChainTables chains[3];  // Ising, XY, Heisenberg members of this slice
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;   // one sweep of the per-sweep chains
+    hipGraphExec_t pexec = nullptr;  // persistent launch of the Ising chain (all sweeps of a call)
     hipStream_t stream = nullptr;  // internal, default priority
     hipEvent_t join = nullptr;
 };
@@ -279,6 +329,16 @@ struct pyro_sw_group {
     RepState **d_members = nullptr;  // state pointer of every member (stream-ordered allocation)
     bool broken = false;
     Timer timer;
+    // Ising modes (pyro_sw_group_set_mode): persistent fused launch for the
+    // tiled Ising members; LDS-resident launch for small Ising members
+    int ising_mode = PYRO_MODE_GRAPH;
+    int64_t persist_cap = kRing;  // sweeps per persistent launch (item counts stay below 2^31)
+    bool resident = false;
+    ChainTables res;  // LDS-resident members (one launch, own stream)
+    int res_maxL = 0;
+    hipGraphExec_t rexec = nullptr;
+    hipStream_t res_stream = nullptr;
+    hipEvent_t res_join = nullptr;
 };
 
 namespace {
@@ -387,11 +447,27 @@ void free_tables(ChainTables &ct)
     ct.d_desc = nullptr;
     ct.d_stp = nullptr;
     ct.d_tile_rep = ct.d_cblk_rep = nullptr;
+    ct.d_ctl = nullptr;
 }
 
-// Build (or rebuild) the device tables of a group chain on stream st; the
-// copies are complete when this returns.
-hipError_t build_group_chain(ChainTables &ct, int shape, hipStream_t st)
+// Workgroups of a persistent launch with tile shape `shape`: all that can
+// be resident on the current device.
+int persist_grid_for(int shape)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ising_persistent_blocks_per_cu(shape, &per_cu) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return std::max(1, cus * std::max(per_cu, 1));
+}
+
+// Build (or rebuild) the device tables of a group chain on stream st (with
+// the control words of a persistent launch when `persistent`); the copies
+// are complete when this returns.
+hipError_t build_group_chain(ChainTables &ct, int shape, hipStream_t st, bool persistent = false)
 {
     free_tables(ct);
     ct.owned = true;
@@ -420,13 +496,17 @@ hipError_t build_group_chain(ChainTables &ct, int shape, hipStream_t st)
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_desc = up(sizeof(RepDesc) * n), b_stp = up(sizeof(RepState *) * n);
     const size_t b_t = up(sizeof(int) * tmap.size()), b_c = up(sizeof(int) * cmap.size());
-    hipError_t e = hipMallocAsync(&ct.block, b_desc + b_stp + b_t + b_c, st);
+    const size_t b_ctl = persistent ? up(sizeof(int) * kPersistStride * (n + 1)) : 0;
+    hipError_t e = hipMallocAsync(&ct.block, b_desc + b_stp + b_t + b_c + b_ctl, st);
     if (e != hipSuccess) return e;
     char *p = (char *)ct.block;
     ct.d_desc = (RepDesc *)p;
     ct.d_stp = (RepState **)(p + b_desc);
     ct.d_tile_rep = (int *)(p + b_desc + b_stp);
     ct.d_cblk_rep = (int *)(p + b_desc + b_stp + b_t);
+    ct.d_ctl = persistent ? (int *)(p + b_desc + b_stp + b_t + b_c) : nullptr;
+    ct.persist_grid = persistent ? persist_grid_for(shape) : 0;
+    if (persistent && ct.persist_grid == 0) return hipErrorInvalidValue;
     if ((e = hipMemcpyAsync(ct.d_desc, desc.data(), sizeof(RepDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
         return e;
     if ((e = hipMemcpyAsync(ct.d_stp, stp.data(), sizeof(RepState *) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -483,19 +563,19 @@ hipError_t build_solo_chain(pyro_sw *h)
     return hipSuccess;
 }
 
-// Capture one sweep of the given chains on a private stream (nothing runs);
-// the executable graph is later launched on the caller's stream.
-hipError_t capture_sweep(const Chain *chains, int nchains, hipGraphExec_t *exec)
+// Capture the launches `launch(stream)` makes on a private stream (nothing
+// runs); the executable graph is later launched on the caller's stream.
+template <typename F>
+hipError_t capture_graph(F launch, hipGraphExec_t *exec)
 {
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    const LaunchHook none{nullptr, nullptr, nullptr};
     hipError_t le = hipSuccess;
     if (e == hipSuccess) {
-        for (int k = 0; k < nchains && le == hipSuccess; ++k) le = launch_chain_sweep(chains[k], cs, none);
+        le = launch(cs);
         e = hipStreamEndCapture(cs, &graph);
     }
     if (e == hipSuccess && le != hipSuccess) e = le;
@@ -503,6 +583,19 @@ hipError_t capture_sweep(const Chain *chains, int nchains, hipGraphExec_t *exec)
     if (graph) hipGraphDestroy(graph);
     hipStreamDestroy(cs);
     return e;
+}
+
+// Capture one sweep of the given chains.
+hipError_t capture_sweep(const Chain *chains, int nchains, hipGraphExec_t *exec)
+{
+    const LaunchHook none{nullptr, nullptr, nullptr};
+    return capture_graph(
+        [&](hipStream_t cs) {
+            hipError_t le = hipSuccess;
+            for (int k = 0; k < nchains && le == hipSuccess; ++k) le = launch_chain_sweep(chains[k], cs, none);
+            return le;
+        },
+        exec);
 }
 
 // Arming writes replica states in stream order.  The states travel as
@@ -550,6 +643,14 @@ int drain(pyro_sw *h)
     }
     HIP_OR_FAIL(&h->broken, hipStreamSynchronize(h->stream));
     if (h->hs.ring_used > 0) {
+        // The kernels advance the device state exactly as the host mirror
+        // assumes; a persistent launch that gave up a wait leaves it behind.
+        RepState ds{};
+        HIP_OR_FAIL(&h->broken, hipMemcpy(&ds, h->d_state, sizeof(RepState), hipMemcpyDeviceToHost));
+        if (ds.t != h->hs.t || ds.ring_used != h->hs.ring_used) {
+            h->broken = true;
+            return fail(PYRO_EDEVICE, "device sweep state disagrees with the host (a persistent launch gave up)");
+        }
         std::vector<pyro_sw_record> tmp((size_t)h->hs.ring_used);
         HIP_OR_FAIL(&h->broken, hipMemcpy(tmp.data(), h->work + h->ly.ring, sizeof(pyro_sw_record) * tmp.size(),
                                           hipMemcpyDeviceToHost));
@@ -651,11 +752,22 @@ std::string tune_key(const ChainTables &ct)
 
 // (Re)deal a group's members to nslices slices, largest first to the
 // lightest slice; every slice beyond the first gets its own stream.
-static void drop_slices(pyro_sw_group *g)
+static void drop_graphs(pyro_sw_group *g)
 {
     for (auto &sg : g->subs) {
-        if (sg.stream) hipStreamSynchronize(sg.stream);
         if (sg.exec) hipGraphExecDestroy(sg.exec);
+        if (sg.pexec) hipGraphExecDestroy(sg.pexec);
+        sg.exec = sg.pexec = nullptr;
+    }
+    if (g->rexec) hipGraphExecDestroy(g->rexec);
+    g->rexec = nullptr;
+}
+
+static void drop_slices(pyro_sw_group *g)
+{
+    drop_graphs(g);
+    for (auto &sg : g->subs) {
+        if (sg.stream) hipStreamSynchronize(sg.stream);
         for (auto &ct : sg.chains) free_tables(ct);
         if (sg.join) hipEventDestroy(sg.join);
         if (sg.stream) hipStreamDestroy(sg.stream);
@@ -663,22 +775,44 @@ static void drop_slices(pyro_sw_group *g)
     g->subs.clear();
 }
 
-static int make_slices(pyro_sw_group *g, int nslices)
+// Small pure Ising lattices sweep LDS-resident when the group asks for it.
+static bool resident_member(const pyro_sw_group *g, const pyro_sw *h)
 {
-    const int n = (int)g->members.size();
-    drop_slices(g);
-    g->subs.resize(nslices);
+    return g->resident && h->model == PYRO_ISING && h->L <= kResidentMaxL && !h->diluted;
+}
+
+// Deal the members to the slices, largest first to the lightest slice (the
+// LDS-resident ones to their own launch).
+static void deal_members(pyro_sw_group *g)
+{
+    const int n = (int)g->members.size(), nslices = (int)g->subs.size();
+    for (auto &sg : g->subs)
+        for (auto &ct : sg.chains) ct.reps.clear();
+    g->res.reps.clear();
+    g->res.model = PYRO_ISING;
+    g->res_maxL = 0;
     std::vector<double> load(nslices, 0.0);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return g->members[a]->N > g->members[b]->N; });
     for (int i : order) {
-        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += (double)g->members[i]->N;
         pyro_sw *h = g->members[i];
+        if (resident_member(g, h)) {
+            g->res.reps.push_back(h);
+            g->res_maxL = std::max(g->res_maxL, h->L);
+            continue;
+        }
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += (double)h->N;
         g->subs[k].chains[h->model - 1].reps.push_back(h);
     }
+}
+
+static int make_slices(pyro_sw_group *g, int nslices)
+{
+    drop_slices(g);
+    g->subs.resize(nslices);
     bool ok = g->fork || hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
     for (auto &sg : g->subs) {
         for (int m = 0; m < 3; ++m) sg.chains[m].model = m + 1;
@@ -687,6 +821,7 @@ static int make_slices(pyro_sw_group *g, int nslices)
             ok = ok && hipEventCreateWithFlags(&sg.join, hipEventDisableTiming) == hipSuccess;
         }
     }
+    deal_members(g);
     g->tables_dirty = true;
     if (!ok) {
         (void)hipGetLastError();
@@ -1042,6 +1177,58 @@ int pyro_sw_sweep_static(void *dev_spins, int L, int model, double T, double J, 
     return PYRO_OK;
 }
 
+int pyro_sw_atomic_rate(int mode, int64_t words, int64_t ops, int repeats, double *ops_per_second,
+                        int64_t *succeeded, int64_t *word_sum)
+{
+    if (mode != 0 && mode != 1) return fail(PYRO_EINVAL, "mode must be 0 (random CAS) or 1 (one-address add)");
+    if (words < 1 || words > ((int64_t)1 << 32)) return fail(PYRO_EINVAL, "words must be in [1, 2^32]");
+    if (ops < 1 || ops > ((int64_t)1 << 40)) return fail(PYRO_EINVAL, "ops must be in [1, 2^40]");
+    if (repeats < 1) return fail(PYRO_EINVAL, "repeats must be >= 1");
+    if (!ops_per_second || !succeeded || !word_sum) return fail(PYRO_EINVAL, "outputs must not be NULL");
+    constexpr int kBlocks = 4096;  // 16 workgroups of 256 threads per CU
+    uint32_t *a = nullptr;
+    unsigned long long *d_out = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best = -1.0f;
+    unsigned long long out[2] = {0, 0};
+    hipError_t e = hipMalloc(&a, sizeof(uint32_t) * (size_t)words);
+    if (e == hipSuccess) e = hipMalloc(&d_out, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int r = 0; r < repeats && e == hipSuccess; ++r) {
+        e = hipMemsetAsync(a, 0, sizeof(uint32_t) * (size_t)words, st);
+        if (e == hipSuccess) e = hipMemsetAsync(d_out, 0, 2 * sizeof(unsigned long long), st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess) {
+            k_atomic_rate<<<kBlocks, 256, 0, st>>>(mode, a, (uint64_t)words, (uint64_t)ops, d_out);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) {
+            k_sum_words<<<1024, 256, 0, st>>>(a, (uint64_t)words, d_out + 1);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best < 0.0f || ms < best)) best = ms;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof(out), hipMemcpyDeviceToHost);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (st) (void)hipStreamDestroy(st);
+    if (d_out) (void)hipFree(d_out);
+    if (a) (void)hipFree(a);
+    if (e != hipSuccess) return fail(PYRO_EDEVICE, std::string("atomic rate: ") + hipGetErrorString(e));
+    *succeeded = (int64_t)out[0];
+    *word_sum = (int64_t)out[1];
+    *ops_per_second = (double)ops / (std::max(best, 1e-6f) * 1e-3);
+    return PYRO_OK;
+}
+
 int pyro_sw_destroy(pyro_sw *h)
 {
     if (!h) return PYRO_OK;
@@ -1103,7 +1290,11 @@ int pyro_sw_group_create(pyro_sw_group **out, pyro_sw *const *members, int n, vo
         auto it = g_tune_cache.find(tune_key(ct));
         int lmax = 1;
         for (const pyro_sw *h : ct.reps) lmax = std::max(lmax, h->L);
-        ct.shape = it != g_tune_cache.end() ? it->second : default_tile_shape(lmax);
+        ct.shape = it != g_tune_cache.end() ? it->second.shape : default_tile_shape(lmax);
+        if (it != g_tune_cache.end() && ct.model == PYRO_ISING) {
+            g->ising_mode = it->second.ising_mode;
+            g->resident = it->second.resident;
+        }
     }
     if (int rc = make_slices(g, std::min(n, kMaxSlices))) {
         pyro_sw_group_destroy(g);
@@ -1121,13 +1312,24 @@ static int group_prepare(pyro_sw_group *g)
             if (g->seen_versions[i] != g->members[i]->param_version) changed = true;
     if (!changed) return PYRO_OK;
     HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+    drop_graphs(g);
+    deal_members(g);  // a member's dilution decides whether it may stay LDS-resident
+    const bool persistent = g->ising_mode == PYRO_MODE_PERSISTENT;
+    g->persist_cap = kRing;
     for (auto &sg : g->subs) {
-        if (sg.exec) {
-            hipGraphExecDestroy(sg.exec);
-            sg.exec = nullptr;
-        }
         for (int m = 0; m < 3; ++m)
-            HIP_OR_FAIL(&g->broken, build_group_chain(sg.chains[m], g->chains[m].shape, g->stream));
+            HIP_OR_FAIL(&g->broken, build_group_chain(sg.chains[m], g->chains[m].shape, g->stream, m == 0 && persistent));
+        if (persistent)
+            for (const pyro_sw *h : sg.chains[0].reps)
+                g->persist_cap = std::min<int64_t>(g->persist_cap, (INT32_MAX / 4) / tiles_for(h->L, g->chains[0].shape));
+    }
+    HIP_OR_FAIL(&g->broken, build_group_chain(g->res, kTile888, g->stream));
+    if (!g->res.reps.empty() && !g->res_stream) {
+        if (hipStreamCreateWithFlags(&g->res_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&g->res_join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PYRO_EDEVICE, "group stream or event creation failed");
+        }
     }
     g->seen_versions.clear();
     for (auto *h : g->members) g->seen_versions.push_back(h->param_version);
@@ -1135,39 +1337,93 @@ static int group_prepare(pyro_sw_group *g)
     return PYRO_OK;
 }
 
-// Run `reps` armed sweeps: graph replays, or timed direct launches.
+// Does slice sg sweep its Ising chain in one persistent launch per call?
+static bool slice_persistent(const pyro_sw_group *g, const SubGroup &sg)
+{
+    return g->ising_mode == PYRO_MODE_PERSISTENT && sg.chains[0].chain.nreps > 0;
+}
+
+// Chains of slice sg swept by one graph per sweep.
+static int per_sweep_chains(const pyro_sw_group *g, const SubGroup &sg, Chain *cs)
+{
+    int nc = 0;
+    for (int m = 0; m < 3; ++m) {
+        const ChainTables &ct = sg.chains[m];
+        if (ct.chain.nreps == 0 || (m == 0 && slice_persistent(g, sg))) continue;
+        cs[nc++] = ct.chain;
+    }
+    return nc;
+}
+
+// Run `reps` armed sweeps: graph replays (per-sweep graphs `reps` times, the
+// persistent and LDS-resident launches once, since they run every armed
+// sweep themselves), or timed direct launches.
 static int group_run(pyro_sw_group *g, int64_t reps)
 {
     Timer &tm = g->timer;
+    const LaunchHook none{nullptr, nullptr, nullptr};
     if (tm.mask) {  // every kernel in order on the group's stream
         const LaunchHook hook = hook_of(tm, g->stream);
+        if (g->res.chain.nreps > 0)
+            HIP_OR_FAIL(&g->broken, launch_resident_ising(g->res.chain, g->res_maxL, g->stream, hook));
+        for (auto &sg : g->subs)
+            if (slice_persistent(g, sg))
+                HIP_OR_FAIL(&g->broken, launch_ising_persistent(sg.chains[0].chain, sg.chains[0].d_ctl,
+                                                                sg.chains[0].persist_grid, g->stream, hook));
         for (int64_t k = 0; k < reps; ++k) {
-            for (auto &sg : g->subs)
-                for (auto &ct : sg.chains) HIP_OR_FAIL(&g->broken, launch_chain_sweep(ct.chain, g->stream, hook));
+            for (auto &sg : g->subs) {
+                Chain cs[3];
+                const int nc = per_sweep_chains(g, sg, cs);
+                for (int q = 0; q < nc; ++q) HIP_OR_FAIL(&g->broken, launch_chain_sweep(cs[q], g->stream, hook));
+            }
             if (tm.inflight.size() > 8192) HIP_OR_FAIL(&g->broken, tm.collect());
         }
         return PYRO_OK;
     }
     for (auto &sg : g->subs) {
-        if (sg.exec) continue;
         Chain cs[3];
-        int nc = 0;
-        for (auto &ct : sg.chains)
-            if (ct.chain.nreps > 0) cs[nc++] = ct.chain;
-        HIP_OR_FAIL(&g->broken, capture_sweep(cs, nc, &sg.exec));
+        const int nc = per_sweep_chains(g, sg, cs);
+        if (!sg.exec && nc > 0) HIP_OR_FAIL(&g->broken, capture_sweep(cs, nc, &sg.exec));
+        if (!sg.pexec && slice_persistent(g, sg)) {
+            const ChainTables &ct = sg.chains[0];
+            HIP_OR_FAIL(&g->broken, capture_graph(
+                                        [&](hipStream_t cs2) {
+                                            return launch_ising_persistent(ct.chain, ct.d_ctl, ct.persist_grid, cs2,
+                                                                           none);
+                                        },
+                                        &sg.pexec));
+        }
+    }
+    if (!g->rexec && g->res.chain.nreps > 0)
+        HIP_OR_FAIL(&g->broken, capture_graph(
+                                    [&](hipStream_t cs2) { return launch_resident_ising(g->res.chain, g->res_maxL, cs2, none); },
+                                    &g->rexec));
+    auto run_slice = [&](SubGroup &sg, hipStream_t st) -> int {
+        if (sg.pexec) HIP_OR_FAIL(&g->broken, hipGraphLaunch(sg.pexec, st));
+        if (sg.exec)
+            for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(sg.exec, st));
+        return PYRO_OK;
+    };
+    if (g->subs.size() == 1 && !g->rexec) return run_slice(g->subs[0], g->stream);
+    // fork the slices (and the LDS-resident launch) off the group's stream
+    // and join them back
+    HIP_OR_FAIL(&g->broken, hipEventRecord(g->fork, g->stream));
+    if (g->rexec) {
+        HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(g->res_stream, g->fork, 0));
+        HIP_OR_FAIL(&g->broken, hipGraphLaunch(g->rexec, g->res_stream));
+        HIP_OR_FAIL(&g->broken, hipEventRecord(g->res_join, g->res_stream));
     }
     if (g->subs.size() == 1) {
-        for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(g->subs[0].exec, g->stream));
-        return PYRO_OK;
+        if (int rc = run_slice(g->subs[0], g->stream)) return rc;
+    } else {
+        for (auto &sg : g->subs) {
+            HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(sg.stream, g->fork, 0));
+            if (int rc = run_slice(sg, sg.stream)) return rc;
+            HIP_OR_FAIL(&g->broken, hipEventRecord(sg.join, sg.stream));
+            HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(g->stream, sg.join, 0));
+        }
     }
-    // fork the slices off the group's stream and join them back
-    HIP_OR_FAIL(&g->broken, hipEventRecord(g->fork, g->stream));
-    for (auto &sg : g->subs) {
-        HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(sg.stream, g->fork, 0));
-        for (int64_t k = 0; k < reps; ++k) HIP_OR_FAIL(&g->broken, hipGraphLaunch(sg.exec, sg.stream));
-        HIP_OR_FAIL(&g->broken, hipEventRecord(sg.join, sg.stream));
-        HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(g->stream, sg.join, 0));
-    }
+    if (g->rexec) HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(g->stream, g->res_join, 0));
     return PYRO_OK;
 }
 
@@ -1190,7 +1446,7 @@ int pyro_sw_group_sweep(pyro_sw_group *g, int64_t n_sweeps, const int64_t *per_m
     if (rc) return rc;
     for (;;) {
         int64_t chunk = 0;
-        for (int i = 0; i < n; ++i) chunk = std::max(chunk, std::min<int64_t>(want[i], kRing));
+        for (int i = 0; i < n; ++i) chunk = std::max(chunk, std::min<int64_t>(want[i], g->persist_cap));
         if (chunk == 0) break;
         for (int i = 0; i < n; ++i) {
             pyro_sw *h = g->members[i];
@@ -1250,6 +1506,28 @@ int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape)
     return PYRO_OK;
 }
 
+int pyro_sw_group_set_mode(pyro_sw_group *g, int ising_mode, int resident)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (g->broken) return fail(PYRO_ESTATE, "group failed earlier");
+    if (ising_mode != PYRO_MODE_GRAPH && ising_mode != PYRO_MODE_PERSISTENT)
+        return fail(PYRO_EINVAL, "ising_mode must be PYRO_MODE_GRAPH or PYRO_MODE_PERSISTENT");
+    if (ising_mode == PYRO_MODE_PERSISTENT && persist_grid_for(g->chains[0].shape) == 0)
+        return fail(PYRO_EDEVICE, "no persistent launch fits the device");
+    g->ising_mode = ising_mode;
+    g->resident = resident != 0;
+    g->tables_dirty = true;
+    return PYRO_OK;
+}
+
+int pyro_sw_group_get_mode(const pyro_sw_group *g, int *ising_mode, int *resident)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (ising_mode) *ising_mode = g->ising_mode;
+    if (resident) *resident = g->resident ? 1 : 0;
+    return PYRO_OK;
+}
+
 int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out)
 {
     if (!g) return fail(PYRO_EINVAL, "group is NULL");
@@ -1280,15 +1558,32 @@ int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out)
     for (int m = 0; m < 3 && rc == PYRO_OK; ++m) {
         ChainTables &ct = g->chains[m];
         if (ct.reps.empty()) continue;
+        // candidates: every tile shape per-sweep; for Ising also the
+        // persistent launch with the shapes whose workgroups fit it well,
+        // each with and without the LDS-resident small lattices
+        std::vector<TuneChoice> cands;
+        bool small = false;
+        for (const pyro_sw *h : ct.reps) small |= h->model == PYRO_ISING && h->L <= kResidentMaxL && !h->diluted;
+        for (int res = 0; res < ((m == 0 && small) ? 2 : 1); ++res) {
+            for (int s = 0; s < kNumTileShapes; ++s) cands.push_back({s, PYRO_MODE_GRAPH, res != 0});
+            if (m == 0)
+                for (int s : {kTile888, kTile884, kTile844})
+                    if (persist_grid_for(s) > 0) cands.push_back({s, PYRO_MODE_PERSISTENT, res != 0});
+        }
         double best = 1e300;
-        int best_shape = ct.shape;
+        TuneChoice best_c{ct.shape, g->ising_mode, g->resident};
         std::vector<int64_t> per(n, 0);
         for (int i = 0; i < n; ++i)
             if (g->members[i]->model == m + 1) per[i] = trial_sweeps;
-        for (int s = 0; s < kNumTileShapes && rc == PYRO_OK; ++s) {
-            ct.shape = s;
+        for (const TuneChoice &cand : cands) {
+            if (rc != PYRO_OK) break;
+            ct.shape = cand.shape;
+            if (m == 0) {
+                g->ising_mode = cand.ising_mode;
+                g->resident = cand.resident;
+            }
             g->tables_dirty = true;
-            rc = pyro_sw_group_sweep(g, 0, per.data());  // builds tables and graph, warms caches
+            rc = pyro_sw_group_sweep(g, 0, per.data());  // builds tables and graphs, warms caches
             if (rc) break;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             hipEventCreate(&e0);
@@ -1303,13 +1598,17 @@ int pyro_sw_group_autotune(pyro_sw_group *g, int trial_sweeps, int *shapes_out)
             hipEventDestroy(e1);
             if (rc == PYRO_OK && ms < best) {
                 best = ms;
-                best_shape = s;
+                best_c = cand;
             }
         }
-        ct.shape = best_shape;
+        ct.shape = best_c.shape;
+        if (m == 0) {
+            g->ising_mode = best_c.ising_mode;
+            g->resident = best_c.resident;
+        }
         g->tables_dirty = true;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[tune_key(ct)] = best_shape;
+        g_tune_cache[tune_key(ct)] = best_c;
     }
     // Restore every member exactly, dropping the trial records.
     hipStreamSynchronize(g->stream);
@@ -1352,6 +1651,12 @@ int pyro_sw_group_destroy(pyro_sw_group *g)
     if (g->stream && hipStreamSynchronize(g->stream) != hipSuccess) rc = fail(PYRO_EDEVICE, "synchronize failed");
     g->timer.release();
     drop_slices(g);
+    free_tables(g->res);
+    if (g->res_stream) {
+        hipStreamSynchronize(g->res_stream);
+        hipStreamDestroy(g->res_stream);
+    }
+    if (g->res_join) hipEventDestroy(g->res_join);
     if (g->fork) hipEventDestroy(g->fork);
     if (g->d_members) hipFreeAsync(g->d_members, g->stream);
     if (g->own_stream) hipStreamDestroy(g->stream);

@@ -683,24 +683,30 @@ constexpr int kForestThreads = 512;  // threads per tile in the unite and store 
 __device__ __forceinline__ int lds_ld(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ __forceinline__ void lds_st(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
-__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid)
+// LDS of the unite pass of one tile.
+struct UniteLds {
+    static constexpr int kMaxListed = 1024;  // pairs kept in LDS
+    int HK[kTileRoots];           // local root of the slot, -1 if free
+    int HP[kTileRoots];           // LDS parent slot
+    uint64_t BEST[kTileRoots];    // per group: smallest member << 10 | its slot
+    int16_t PA[kMaxListed], PB[kMaxListed];
+    int nroots, missed;
+};
+
+template <int NT>
+__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid, UniteLds &S)
 {
-    constexpr int H = kTileRoots;     // root slots
-    constexpr int kMaxListed = 1024;  // pairs kept in LDS
-    __shared__ int HK[H];             // local root of the slot, -1 if free
-    __shared__ int HP[H];             // LDS parent slot
-    __shared__ uint64_t BEST[H];      // per group: smallest member << 10 | its slot
-    __shared__ int16_t PA[kMaxListed], PB[kMaxListed];
-    __shared__ int nroots, missed;
+    constexpr int H = kTileRoots;                    // root slots
+    constexpr int kMaxListed = UniteLds::kMaxListed;  // pairs kept in LDS
     const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
-    for (int k = tid; k < H; k += kForestThreads) {
-        HK[k] = -1;
-        HP[k] = k;
-        BEST[k] = ~0ull;
+    for (int k = tid; k < H; k += NT) {
+        S.HK[k] = -1;
+        S.HP[k] = k;
+        S.BEST[k] = ~0ull;
     }
     if (tid == 0) {
-        nroots = 0;
-        missed = 0;
+        S.nroots = 0;
+        S.missed = 0;
     }
     __syncthreads();
     auto insert = [&](int key) {
@@ -708,38 +714,38 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         h ^= h >> 15;
         for (int probe = 0; probe < 32; ++probe) {
             const int slot = (int)((h + (uint32_t)probe) & (H - 1));
-            int prev = lds_ld(&HK[slot]);
-            if (prev == -1) prev = atomicCAS(&HK[slot], -1, key);
+            int prev = lds_ld(&S.HK[slot]);
+            if (prev == -1) prev = atomicCAS(&S.HK[slot], -1, key);
             if (prev == -1 || prev == key) return slot;
         }
         return -1;
     };
-    for (int k = tid; k < n; k += kForestThreads) {
+    for (int k = tid; k < n; k += NT) {
         const int2 p = list[k];
         const int ra = name_root(lab, p.x), rb = name_root(lab, p.y);
         const int sa = ra == rb ? -1 : insert(ra), sb = ra == rb ? -1 : insert(rb);
         const bool listed = k < kMaxListed && sa >= 0 && sb >= 0;
         if (!listed && ra != rb) forest_unite(lab, ra, rb);
-        if (ra != rb && (sa < 0 || sb < 0)) missed = 1;
+        if (ra != rb && (sa < 0 || sb < 0)) S.missed = 1;
         if (k < kMaxListed) {
-            PA[k] = (int16_t)(listed ? sa : -1);
-            PB[k] = (int16_t)(listed ? sb : -1);
+            S.PA[k] = (int16_t)(listed ? sa : -1);
+            S.PB[k] = (int16_t)(listed ? sb : -1);
         }
     }
     __syncthreads();
     auto slot_find = [&](int x) {
         for (int it = 0; it < H; ++it) {
-            const int p = lds_ld(&HP[x]);
+            const int p = lds_ld(&S.HP[x]);
             if (p == x) return x;
-            const int gp = lds_ld(&HP[p]);
-            if (gp != p) lds_st(&HP[x], gp);
+            const int gp = lds_ld(&S.HP[p]);
+            if (gp != p) lds_st(&S.HP[x], gp);
             x = p;
         }
         return x;
     };
     const int nl = min(n, kMaxListed);
-    for (int k = tid; k < nl; k += kForestThreads) {
-        int a = PA[k], b = PB[k];
+    for (int k = tid; k < nl; k += NT) {
+        int a = S.PA[k], b = S.PB[k];
         if (a < 0) continue;
         for (int it = 0; it < H; ++it) {
             a = slot_find(a);
@@ -750,65 +756,55 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
                 a = b;
                 b = t;
             }
-            const int old = atomicMin(&HP[a], b);
+            const int old = atomicMin(&S.HP[a], b);
             if (old == a) break;
             a = old;
         }
     }
     __syncthreads();
-    for (int s = tid; s < H; s += kForestThreads) {
-        if (HK[s] < 0) continue;
-        atomicMin(&BEST[slot_find(s)], (uint64_t)HK[s] << 10 | (uint64_t)s);
+    for (int s = tid; s < H; s += NT) {
+        if (S.HK[s] < 0) continue;
+        atomicMin(&S.BEST[slot_find(s)], (uint64_t)S.HK[s] << 10 | (uint64_t)s);
     }
     __syncthreads();
     // The pairs are read: overwrite them with the distinct local roots (at
     // most 2n of them, so they fit where the pairs were); PA now holds each
     // slot's list position.
     const bool with_reps = list_stride >= 2 + 2 * H;
-    if (!missed) {
-        for (int s = tid; s < H; s += kForestThreads) {
-            if (HK[s] < 0) continue;
-            const int j = atomicAdd(&nroots, 1);
-            PA[s] = (int16_t)j;
-            head[2 + j] = HK[s];
+    if (!S.missed) {
+        for (int s = tid; s < H; s += NT) {
+            if (S.HK[s] < 0) continue;
+            const int j = atomicAdd(&S.nroots, 1);
+            S.PA[s] = (int16_t)j;
+            head[2 + j] = S.HK[s];
         }
     }
     __syncthreads();
-    for (int s = tid; s < H; s += kForestThreads) {
-        if (HK[s] < 0) continue;
-        const int rs = (int)(BEST[slot_find(s)] & (uint64_t)(H - 1));
-        if (!missed && with_reps) head[2 + H + PA[s]] = PA[rs];
-        if (rs != s) forest_unite(lab, HK[s], HK[rs]);
+    for (int s = tid; s < H; s += NT) {
+        if (S.HK[s] < 0) continue;
+        const int rs = (int)(S.BEST[slot_find(s)] & (uint64_t)(H - 1));
+        if (!S.missed && with_reps) head[2 + H + S.PA[s]] = S.PA[rs];
+        if (rs != s) forest_unite(lab, S.HK[s], S.HK[rs]);
     }
-    if (tid == 0) head[1] = missed ? 0 : (with_reps ? -nroots : nroots);
+    if (tid == 0) head[1] = S.missed ? 0 : (with_reps ? -S.nroots : S.nroots);
 }
 
-template <int PASS>
-__global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
+// Store pass of one tile (NT threads; HK: kTileRoots ints of LDS).
+template <int NT>
+__device__ __forceinline__ void store_tile(const RepDesc &d, const RepState &st, int tile, int tid, int *HK)
 {
     constexpr int H = kTileRoots;
-    __shared__ int HK[PASS == kPassUnite ? 1 : H];
-    const int rep = c.tile_rep[blockIdx.x];
-    const RepState st = *c.state[rep];
-    if (st.remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
     int *head = d.pairs + (int64_t)tile * d.list_stride;
     const int2 *list = reinterpret_cast<const int2 *>(head) + 1;
     const int n = head[0];
-    const int tid = threadIdx.x;
     int32_t *lab = d.label;
-    if (PASS == kPassUnite) {
-        unite_tile_pairs(lab, head, n, d.list_stride, tid);
-        return;
-    }
     if (n == 0) return;
     const int nroots = head[1];  // != 0: the list holds the tile's distinct local roots
     if (nroots < 0) {
         // with group representatives: one walk per group, then plain stores
         const int m = -nroots;
         const int *rp = head + 2 + H;
-        for (int k = tid; k < m; k += kForestThreads) {
+        for (int k = tid; k < m; k += NT) {
             if (rp[k] != k) continue;
             const int r = head[2 + k];
             const int e = canon_encoding(lab, r, st.t, d.key);
@@ -816,12 +812,12 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
             lab_store(lab, r, e);
         }
         __syncthreads();
-        for (int k = tid; k < m; k += kForestThreads)
+        for (int k = tid; k < m; k += NT)
             if (rp[k] != k) lab_store(lab, head[2 + k], HK[rp[k]]);
         return;
     }
     if (nroots > 0) {
-        for (int k = tid; k < nroots; k += kForestThreads) {
+        for (int k = tid; k < nroots; k += NT) {
             const int r = head[2 + k];
             lab_store(lab, r, canon_encoding(lab, r, st.t, d.key));
         }
@@ -829,7 +825,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
     }
     // The list kept its pairs: store once per distinct local root, found
     // through an LDS hash table (a full table stores directly).
-    for (int k = tid; k < H; k += kForestThreads) HK[k] = -1;
+    for (int k = tid; k < H; k += NT) HK[k] = -1;
     __syncthreads();
     auto add = [&](int key) {
         uint32_t h = (uint32_t)key * 0x9E3779B1u;
@@ -842,15 +838,39 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
         }
         lab_store(lab, key, canon_encoding(lab, key, st.t, d.key));
     };
-    for (int k = tid; k < 2 * n; k += kForestThreads) {
+    for (int k = tid; k < 2 * n; k += NT) {
         const int2 p = list[k >> 1];
         add(name_root(lab, (k & 1) ? p.y : p.x));
     }
     __syncthreads();
-    for (int k = tid; k < H; k += kForestThreads) {
+    for (int k = tid; k < H; k += NT) {
         const int key = HK[k];
         if (key >= 0) lab_store(lab, key, canon_encoding(lab, key, st.t, d.key));
     }
+}
+
+// Unite pass of one tile (NT threads).
+template <int NT>
+__device__ __forceinline__ void unite_tile(const RepDesc &d, int tile, int tid, UniteLds &S)
+{
+    int *head = d.pairs + (int64_t)tile * d.list_stride;
+    unite_tile_pairs<NT>(d.label, head, head[0], d.list_stride, tid, S);
+}
+
+template <int PASS>
+__global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
+{
+    __shared__ union {
+        UniteLds u;
+        int HK[kTileRoots];
+    } S;
+    const int rep = c.tile_rep[blockIdx.x];
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    const int tile = blockIdx.x - d.tile_base;
+    if (PASS == kPassUnite) unite_tile<kForestThreads>(d, tile, threadIdx.x, S.u);
+    else store_tile<kForestThreads>(d, st, tile, threadIdx.x, S.HK);
 }
 
 // Shape dispatch: calls F::template run<TX, TY, TZ>(args...).

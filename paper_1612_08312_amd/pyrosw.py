@@ -44,16 +44,17 @@ EXPORTS = (
     "pyro_sw_destroy", "pyro_sw_strerror", "pyro_sw_last_error", "pyro_sw_set_tile_shape",
     "pyro_sw_group_create", "pyro_sw_group_sweep", "pyro_sw_group_autotune",
     "pyro_sw_group_set_tile_shape", "pyro_sw_group_set_timing", "pyro_sw_group_kernel_times",
-    "pyro_sw_group_destroy", "pyro_sw_group_set_slices",
+    "pyro_sw_group_destroy", "pyro_sw_group_set_slices", "pyro_sw_group_set_mode", "pyro_sw_group_get_mode",
     "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
     "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
-    "pyro_sw_philox_rate", "pyro_sw_sweep_static",
+    "pyro_sw_philox_rate", "pyro_sw_sweep_static", "pyro_sw_atomic_rate",
     "pyro_sw_graph_init", "pyro_sw_graph_sweep", "pyro_sw_graph_moments", "pyro_sw_graph_get_spins",
     "pyro_sw_graph_set_spins", "pyro_sw_graph_get_labels", "pyro_sw_graph_set_temperature",
     "pyro_sw_graph_destroy", "pyro_sw_bonds", "pyro_sw_sc_bonds",
 )
 
 PYRO_JOB_QUEUED, PYRO_JOB_RUNNING, PYRO_JOB_DONE = 0, 1, 2
+PYRO_MODE_GRAPH, PYRO_MODE_PERSISTENT = 0, 1
 
 
 class JobSpec(ctypes.Structure):
@@ -117,12 +118,15 @@ def load_library():
     lib.pyro_sw_destroy.argtypes = [vp]
     lib.pyro_sw_philox_rate.argtypes = [i64, i32, u64, P(f64), P(ctypes.c_uint32)]
     lib.pyro_sw_sweep_static.argtypes = [vp, i32, i32, f64, f64, u64, i64, i64, vp, vp]
+    lib.pyro_sw_atomic_rate.argtypes = [i32, i64, i64, i32, P(f64), P(i64), P(i64)]
     lib.pyro_sw_set_tile_shape.argtypes = [vp, i32]
     lib.pyro_sw_group_create.argtypes = [P(vp), P(vp), i32, vp]
     lib.pyro_sw_group_sweep.argtypes = [vp, i64, P(i64)]
     lib.pyro_sw_group_autotune.argtypes = [vp, i32, P(i32)]
     lib.pyro_sw_group_set_tile_shape.argtypes = [vp, i32, i32]
     lib.pyro_sw_group_set_slices.argtypes = [vp, i32]
+    lib.pyro_sw_group_set_mode.argtypes = [vp, i32, i32]
+    lib.pyro_sw_group_get_mode.argtypes = [vp, P(i32), P(i32)]
     lib.pyro_sw_group_set_timing.argtypes = [vp, i32]
     lib.pyro_sw_group_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_group_destroy.argtypes = [vp]
@@ -310,6 +314,16 @@ def pyro_sw_group_set_slices(g, nslices: int):
     _check(load_library().pyro_sw_group_set_slices(g, int(nslices)), "pyro_sw_group_set_slices")
 
 
+def pyro_sw_group_set_mode(g, ising_mode: int, resident: bool = False):
+    _check(load_library().pyro_sw_group_set_mode(g, int(ising_mode), int(bool(resident))), "pyro_sw_group_set_mode")
+
+
+def pyro_sw_group_get_mode(g):
+    m, r = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().pyro_sw_group_get_mode(g, ctypes.byref(m), ctypes.byref(r)), "pyro_sw_group_get_mode")
+    return m.value, bool(r.value)
+
+
 def pyro_sw_group_destroy(g):
     if g is not None and g.value:
         _check(load_library().pyro_sw_group_destroy(g), "pyro_sw_group_destroy")
@@ -333,6 +347,16 @@ def pyro_sw_sweep_static(dev_spins: int, L, model, T, J, seed, first_sweep, n_sw
     _check(load_library().pyro_sw_sweep_static(int(dev_spins), int(L), int(model), float(T), float(J), int(seed),
                                                int(first_sweep), int(n_sweeps), int(dev_records),
                                                _stream_ptr(stream)), "pyro_sw_sweep_static")
+
+
+def pyro_sw_atomic_rate(mode: int, words: int, ops: int, repeats: int = 3):
+    """Device atomic operations per second (mode 0: load + compare-and-swap
+    of random words of a `words`-word array; mode 1: adds to one word), the
+    number of operations that took effect and the array's sum afterwards."""
+    rate, ok, total = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().pyro_sw_atomic_rate(int(mode), int(words), int(ops), int(repeats), ctypes.byref(rate),
+                                              ctypes.byref(ok), ctypes.byref(total)), "pyro_sw_atomic_rate")
+    return rate.value, ok.value, total.value
 
 
 def pyro_sw_destroy(h):
@@ -430,6 +454,13 @@ class Group:
 
     def set_slices(self, nslices):
         pyro_sw_group_set_slices(self.g, nslices)
+
+    def set_mode(self, ising_mode, resident=False):
+        pyro_sw_group_set_mode(self.g, ising_mode, resident)
+
+    def mode(self):
+        """(Ising mode, LDS-resident small lattices)."""
+        return pyro_sw_group_get_mode(self.g)
 
     def close(self):
         if getattr(self, "g", None) is not None:

@@ -151,3 +151,11 @@ def test_graph_init_rejects_bad_arguments_without_a_device(bonds, n, model):
     rc = lib.pyro_sw_graph_init(ctypes.byref(h), n, len(a), a.ctypes.data_as(ctypes.c_void_p),
                                 b.ctypes.data_as(ctypes.c_void_p), model, 4.0, 1.0, 1, 0, None)
     assert rc == pyrosw.PYRO_EINVAL and not h.value
+
+
+@pytest.mark.parametrize("args", [(2, 16, 16, 1), (0, 0, 16, 1), (0, (1 << 32) + 1, 16, 1), (0, 16, 0, 1),
+                                  (1, 16, 16, 0)])
+def test_atomic_rate_rejects_bad_arguments_without_a_device(args):
+    with pytest.raises(pyrosw.PyroSWError) as ei:
+        pyrosw.pyro_sw_atomic_rate(*args)
+    assert ei.value.status == pyrosw.PYRO_EINVAL

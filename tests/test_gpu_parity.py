@@ -190,6 +190,28 @@ def test_ising_l128_benched_group_form_bit_exact():
     grp.close()
     for lt in lats:
         lt.close()
+
+
+def test_ising_l128_persistent_group_bit_exact():
+    """The five L = 128 lattices in one persistent fused launch per call
+    (8x8x8 tiles, one slice): three sweeps in one call, every member's
+    records, spins and labels equal the oracle's."""
+    c = workloads.ISING_L128
+    lats = [gpu_lattice(L=128, model=1, T=T, seed=s, start=c["start"]) for T, s in zip(c["temps"], c["seeds"])]
+    grp = pyrosw.Group(lats)
+    grp.set_slices(1)
+    grp.set_tile_shape(1, pyrosw.PYRO_TILE_8x8x8)
+    grp.set_mode(pyrosw.PYRO_MODE_PERSISTENT)
+    grp.sweep(3)
+    for k, lt in enumerate(lats):
+        ref = l128_oracle(k)
+        assert_records_exact(lt.moments(), ref["rec"])
+        np.testing.assert_array_equal(lt.spins(), ref["s3"])
+        np.testing.assert_array_equal(lt.labels(), ref["l3"])
+        say(f"persistent group form: member {k} bit-exact")
+    grp.close()
+    for lt in lats:
+        lt.close()
     _L128_ORACLE.clear()
 
 

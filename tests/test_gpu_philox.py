@@ -29,3 +29,12 @@ def test_device_philox_fold_matches_oracle(seed):
     rate, fold = pyrosw.pyro_sw_philox_rate(calls, repeats=1, seed=seed)
     assert rate > 0
     assert fold == oracle_fold(calls, seed)
+
+
+def test_atomic_rate_loses_no_update():
+    """The atomic-throughput probe: every successful compare-and-swap shows
+    in the array's sum, and one-address adds count every operation."""
+    rate, ok, total = pyrosw.pyro_sw_atomic_rate(0, 1 << 20, 1 << 22, 1)
+    assert rate > 0 and 0 < ok <= 1 << 22 and total == ok
+    rate, ok, total = pyrosw.pyro_sw_atomic_rate(1, 1, 1 << 20, 1)
+    assert rate > 0 and ok == 1 << 20 and total == 1 << 20

@@ -8,7 +8,8 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from paper_1612_08312_amd import pyrosw, serving  # noqa: E402
+import oracle  # noqa: E402
+from paper_1612_08312_amd import pyrosw, serving, workloads  # noqa: E402
 
 
 def _alone(job):
@@ -114,3 +115,43 @@ def test_server_rejects_a_job_larger_than_the_budget():
     with pytest.raises(pyrosw.PyroSWError):
         srv.status(jid)  # taken jobs are forgotten
     srv.close()
+
+
+def test_served_small_jobs_match_the_oracle():
+    """Jobs drawn like the serving stream's (model uniform over the three,
+    T within 2% of each model's T_c, their seeds and random start), two of
+    every three shrunk to L = 2..8 and the others kept up to L = 40 so that
+    several lanes run at once; every small job's records and final spins,
+    served with continuous batching, against the oracle (Ising bit-exact,
+    O(n) records within 1e-5 and spins within 1e-5)."""
+    jobs = []
+    for k, j in enumerate(workloads.serving_jobs(n_jobs=30)):
+        if j["L"] > 128:
+            continue
+        j = dict(j, arrival=0.002 * k, sweeps=min(j["sweeps"], 120))
+        j["L"] = 2 + (j["L"] // 8) % 7 if k % 3 else min(j["L"], 40)
+        jobs.append(j)
+    srv = pyrosw.Server(hbm_budget=4 << 30, max_running=64, quantum_ms=2.0)
+    results, _ = serving.run_stream(srv, jobs, keep_spins=True)
+    srv.close()
+    checked = 0
+    for r in results:
+        j = r["job"]
+        if j["L"] > 8:
+            continue
+        o = oracle.Oracle(L=j["L"], model=j["model"], T=j["T"], J=j["J"], seed=j["seed"], start=j["start"])
+        orec = o.sweep(j["sweeps"])
+        rec = r["records"]
+        assert len(rec) == len(orec) == j["sweeps"]
+        np.testing.assert_array_equal(rec["sweep"], orec["sweep"])
+        if j["model"] == pyrosw.PYRO_ISING:
+            for f in ("bond_sum", "M_int", "E", "M", "m2", "m4"):
+                np.testing.assert_array_equal(rec[f], orec[f], err_msg=f"job {j['job_id']} {f}")
+            np.testing.assert_array_equal(r["spins"].view(np.int8), o.spins())
+        else:
+            for f in ("E", "m2", "m4"):
+                np.testing.assert_allclose(rec[f], orec[f], rtol=1e-5, atol=1e-9, err_msg=f"job {j['job_id']} {f}")
+            np.testing.assert_allclose(r["spins"].view(np.float32).reshape(j["model"], -1), o.spins(),
+                                       rtol=0, atol=1e-5)
+        checked += 1
+    assert checked >= 12
