@@ -50,13 +50,20 @@ def bytes_per_site(shape):
     }
 
 
-# HBM traffic of the dominant kernel per launch (one L=128 lattice), from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of `bench.py --pmc-probe`,
-# each scaled by the same counter's reading for the probe's 256 MiB copy.
-# Valid only for the kernel sources they were taken with (fingerprint).
-MEASURED_TRAFFIC = {  # kernel -> (fingerprint, bytes per launch)
-    "local": ("8776d9e207800e96", 216838352),  # profiles/k_local_ising_L128_traffic.md
-}
+# Per-launch counter figures of the Ising kernels (one L=128 lattice, 8x8x8
+# tiles) from rocprofv3 --pmc runs of `bench.py --pmc-probe`: HBM bytes
+# (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for
+# the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
+# SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
+# taken with (fingerprint); the summaries are in profiles/.
+COUNTER_FINGERPRINT = None
+MEASURED_TRAFFIC = {}  # kernel -> HBM bytes per launch
+MEASURED_ISSUE = {}    # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
+
+# Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a
+# 16-lane SIMD for 4 cycles, so each of the 256 CUs (4 SIMDs) completes at
+# most one wave instruction per cycle: 256 x 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 2.4e9
 
 
 def kernel_fingerprint():
@@ -409,6 +416,51 @@ def graph_throughput(sweeps, stream, dev):
     return out
 
 
+def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs, counters_valid):
+    """Each Ising pass of one L=128 lattice (per-sweep launches, mean over the
+    probe): its duration, what bounds it, and the fraction of that bound it
+    reaches.  The tile pass is bound by VALU issue (wave instructions per
+    launch from the counters / duration, against one wave instruction per CU
+    and cycle); the unite pass by device atomics (compare-and-swaps per launch
+    / duration, against the measured random compare-and-swap rate); the flip
+    by HBM (algorithmic bytes / duration); the store pass by forest walks and
+    scattered stores (counter bytes / duration, against the measured copy
+    bandwidth); the finalize by launch latency (one workgroup per lattice)."""
+    out = {}
+    for k, (n, ms) in kt.items():
+        if not n:
+            continue
+        us = ms / n * 1e3
+        row = {"us": round(us, 2)}
+        if k == "local":
+            row["bound"] = "VALU issue"
+            if counters_valid and k in MEASURED_ISSUE:
+                valu, salu, waves = MEASURED_ISSUE[k]
+                row.update(valu_per_wave=round(valu / waves), salu_per_wave=round(salu / waves),
+                           achieved_wave_instr_per_s=valu / (us * 1e-6), peak_wave_instr_per_s=VALU_ISSUE_PEAK,
+                           frac=valu / (us * 1e-6) / VALU_ISSUE_PEAK)
+            row["hbm_alg_frac"] = 5.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9)
+        elif k == "unite":
+            row.update(bound="device atomics", cas_per_launch=round(cas_per_launch),
+                       hooks_per_launch=round(hooks_per_launch), achieved_cas_per_s=cas_per_launch / (us * 1e-6),
+                       peak_cas_per_s=cas_ceiling, frac=cas_per_launch / (us * 1e-6) / cas_ceiling)
+        elif k == "flip":
+            row.update(bound="hbm", alg_bytes_per_site=6.0, achieved_GBps=6.0 * N / (us * 1e-6) / 1e9,
+                       peak_GBps=HBM_PEAK_GBS, frac=6.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9))
+        elif k == "canon_store":
+            row["bound"] = "forest walks and scattered 4-byte stores"
+            if counters_valid and k in MEASURED_TRAFFIC:
+                gbs = MEASURED_TRAFFIC[k] / (us * 1e-6) / 1e9
+                row.update(counter_bytes_per_launch=MEASURED_TRAFFIC[k], achieved_GBps=gbs, peak_GBps=copy_gbs,
+                           frac_of_copy=gbs / copy_gbs)
+        elif k == "finalize":
+            row["bound"] = "launch latency (one workgroup per lattice)"
+        if counters_valid and k in MEASURED_TRAFFIC:
+            row["counter_bytes_per_launch"] = MEASURED_TRAFFIC[k]
+        out[k] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,6 +469,10 @@ def main():
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--cpu-sweeps", type=int, default=4, help="oracle sweeps for cpu_baseline (0: skip)")
     ap.add_argument("--tile-shape", type=int, default=-1, help="tile shape id (-1: autotune)")
+    ap.add_argument("--slices", type=int, default=0,
+                    help="concurrent slices of the five-lattice group (0: the group's default, one per lattice)")
+    ap.add_argument("--cas-count-sweeps", type=int, default=4,
+                    help="sweeps of the unite-pass counting run (0: skip; it adds one atomic per swap)")
     ap.add_argument("--ising-mode", choices=("auto", "graph", "persistent"), default="auto",
                     help="Ising sweep mode of the group (auto: the autotuner's choice)")
     ap.add_argument("--batch-sweeps", type=int, default=2000,
@@ -461,6 +517,8 @@ def main():
             for T, s in zip(temps, seeds)]
     N = lats[0].N
     group = pyrosw.Group(lats, stream)
+    if args.slices > 0:
+        group.set_slices(args.slices)
     if args.tile_shape >= 0 or args.ising_mode != "auto":
         tshape = args.tile_shape if args.tile_shape >= 0 else pyrosw.PYRO_TILE_8x8x8
         group.set_tile_shape(1, tshape)
@@ -487,7 +545,7 @@ def main():
     dt = time.perf_counter() - t0
     recs = [lt.moments() for lt in lats]
     # Per-pass breakdown (HIP events on every kernel of per-sweep launches,
-    # three sweeps), then the dominant kernel of the timed mode: the
+    # ten sweeps), then the dominant kernel of the timed mode: the
     # persistent launch itself, or the slowest pass.
     saved_mode = group.mode()
     group.set_mode(pyrosw.PYRO_MODE_GRAPH, saved_mode[1])
@@ -506,6 +564,23 @@ def main():
     pyrosw.pyro_sw_group_set_timing(group.g, 1 << names.index(dominant))
     group.sweep(roof_steps)
     dom_n, dom_ms = pyrosw.pyro_sw_group_kernel_times(group.g)[dominant]
+    pyrosw.pyro_sw_group_set_timing(group.g, 0)
+
+    # Compare-and-swaps of the unite pass per launch (a counting run of
+    # per-sweep launches: one more atomic per swap, so it is not timed) and
+    # the device's random compare-and-swap ceiling on a label-sized array.
+    count_sweeps = args.cas_count_sweeps
+    cas_tried = cas_hooked = 0
+    if count_sweeps > 0:
+        group.set_mode(pyrosw.PYRO_MODE_GRAPH, saved_mode[1])
+        pyrosw.pyro_sw_group_set_counting(group.g, True)
+        group.sweep(count_sweeps)
+        cas_tried, cas_hooked = pyrosw.pyro_sw_group_counts(group.g)
+        pyrosw.pyro_sw_group_set_counting(group.g, False)
+        group.set_mode(*saved_mode)
+        for lt in lats:
+            lt.moments()
+    cas_ceiling, cas_ok, cas_sum = pyrosw.pyro_sw_atomic_rate(0, N, 1 << 26, 3)
     group.close()
     for lt in lats:
         lt.close()
@@ -525,10 +600,8 @@ def main():
     launches_per_step = max(dom_n, 1) / roof_steps
     bytes_per_launch = byte_model.get(dominant, 0.0) * N * len(lats) / launches_per_step
     achieved = bytes_per_launch / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
-    traffic = None
-    fp, tbytes = MEASURED_TRAFFIC.get(dominant, (None, None))
-    if fp == kernel_fingerprint() and launches_per_step == len(lats):
-        traffic = tbytes
+    counters_valid = COUNTER_FINGERPRINT == kernel_fingerprint()
+    traffic = MEASURED_TRAFFIC.get(dominant) if counters_valid and launches_per_step == len(lats) else None
     binder, binder_all = {}, {}
     for T, r in zip(temps, recs):
         half = r[len(r) // 2:]
@@ -557,7 +630,9 @@ def main():
             "seeds": list(seeds),
             "start": "random",
             "sweeps_per_lattice": args.steps,
-            "step": "one SW sweep of each lattice (one captured graph per lattice, run concurrently)",
+            "step": ("one SW sweep of each lattice (every sweep of the timed call in one persistent launch)"
+                     if ising_mode == "persistent" else
+                     "one SW sweep of each lattice (one captured graph per lattice and sweep, run concurrently)"),
             "tile_shape": shape,
             "ising_mode": ising_mode,
         },
@@ -575,6 +650,8 @@ def main():
             "launches_per_step": launches_per_step,
             "copy_GBps": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
+            "limiter": ("the whole sweep in one launch: see kernels" if dominant == "persist" else
+                        "VALU issue and LDS-walk latency, not HBM bandwidth: see kernels.local"),
         },
         "philox": {
             "blocks_per_s": philox_rate,
@@ -584,6 +661,8 @@ def main():
             "fold": philox_fold,
         },
         "sweep_alg_roofline_frac": value * SWEEP_BYTES_PER_SITE / (HBM_PEAK_GBS * 1e9),
+        "kernels": kernel_bounds(kt, N, cas_tried / max(count_sweeps * len(lats), 1),
+                                 cas_hooked / max(count_sweeps * len(lats), 1), cas_ceiling, copy_gbs, counters_valid),
         "binder_U_second_half": binder,
         "binder_U_all_sweeps": binder_all,
         "kernel_mean_us_probe": {k: round(v[1] / v[0] * 1e3, 2) for k, v in kt.items() if v[0]},

@@ -230,6 +230,12 @@ int pyro_sw_kernel_times(pyro_sw *h, const char **names, int64_t *launches, doub
  *   pyro_sw_group_get_mode the current modes (either output may be NULL).
  *   pyro_sw_group_autotune also chooses the Ising modes (every combination
  *                          of mode and tile shape that applies is timed).
+ *   pyro_sw_group_set_counting  on != 0: the unite pass of the tiled sweeps
+ *                          counts its compare-and-swaps on the global forest
+ *                          (a measurement mode: one more device atomic per
+ *                          swap); the counters start at zero.
+ *   pyro_sw_group_counts   synchronises; swaps tried and swaps that hooked a
+ *                          root since counting was switched on (0 if never).
  *   pyro_sw_group_set_timing / pyro_sw_group_kernel_times  as for a handle.
  *   pyro_sw_group_destroy  frees the group only (NULL is a no-op).
  * Errors: PYRO_EINVAL (arguments), PYRO_ESTATE (a member failed or is busy),
@@ -246,6 +252,8 @@ int pyro_sw_group_set_tile_shape(pyro_sw_group *g, int model, int shape);
 int pyro_sw_group_set_slices(pyro_sw_group *g, int nslices);
 int pyro_sw_group_set_mode(pyro_sw_group *g, int ising_mode, int resident);
 int pyro_sw_group_get_mode(const pyro_sw_group *g, int *ising_mode, int *resident);
+int pyro_sw_group_set_counting(pyro_sw_group *g, int on);
+int pyro_sw_group_counts(pyro_sw_group *g, int64_t *cas_tried, int64_t *cas_hooked);
 int pyro_sw_group_set_timing(pyro_sw_group *g, int kernel_mask);
 int pyro_sw_group_kernel_times(pyro_sw_group *g, const char **names, int64_t *launches, double *ms,
                                int cap, int *n_out);

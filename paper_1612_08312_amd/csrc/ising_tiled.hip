@@ -162,7 +162,7 @@ __device__ __forceinline__ void ising_flip_pass(const RepDesc &d, const RepState
     __syncthreads();
     int mag = 0;
     if (valid) {
-        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, st.t, d.key);
+        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
         int4 *S4 = reinterpret_cast<int4 *>(d.spins);
         const int4 sv = S4[cell];
         uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};

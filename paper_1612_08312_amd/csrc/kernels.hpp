@@ -89,6 +89,7 @@ struct Chain {
     int shape;            // TileShape of the tile grid
     int model;            // 1, 2, 3
     int ntile_blocks, ncell_blocks;
+    unsigned long long *counts;  // null, or [2]: compare-and-swaps of the unite pass tried, and that hooked
 };
 
 // Kernel ids for timing (names in init.hip).

@@ -236,7 +236,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
         float r[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
-        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, st.t, d.key);
+        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
         float v[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {

@@ -339,6 +339,8 @@ struct pyro_sw_group {
     hipGraphExec_t rexec = nullptr;
     hipStream_t res_stream = nullptr;
     hipEvent_t res_join = nullptr;
+    unsigned long long *d_counts = nullptr;  // unite-pass compare-and-swap counters (measurement)
+    bool counting = false;
 };
 
 namespace {
@@ -1317,8 +1319,10 @@ static int group_prepare(pyro_sw_group *g)
     const bool persistent = g->ising_mode == PYRO_MODE_PERSISTENT;
     g->persist_cap = kRing;
     for (auto &sg : g->subs) {
-        for (int m = 0; m < 3; ++m)
+        for (int m = 0; m < 3; ++m) {
             HIP_OR_FAIL(&g->broken, build_group_chain(sg.chains[m], g->chains[m].shape, g->stream, m == 0 && persistent));
+            sg.chains[m].chain.counts = g->counting ? g->d_counts : nullptr;
+        }
         if (persistent)
             for (const pyro_sw *h : sg.chains[0].reps)
                 g->persist_cap = std::min<int64_t>(g->persist_cap, (INT32_MAX / 4) / tiles_for(h->L, g->chains[0].shape));
@@ -1520,6 +1524,38 @@ int pyro_sw_group_set_mode(pyro_sw_group *g, int ising_mode, int resident)
     return PYRO_OK;
 }
 
+int pyro_sw_group_set_counting(pyro_sw_group *g, int on)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (g->broken) return fail(PYRO_ESTATE, "group failed earlier");
+    HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+    if (on && !g->d_counts) {
+        if (hipMalloc((void **)&g->d_counts, 2 * sizeof(unsigned long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            g->d_counts = nullptr;
+            return fail(PYRO_ENOMEM, "counters");
+        }
+    }
+    if (on) HIP_OR_FAIL(&g->broken, hipMemset(g->d_counts, 0, 2 * sizeof(unsigned long long)));
+    g->counting = on != 0;
+    g->tables_dirty = true;
+    return PYRO_OK;
+}
+
+int pyro_sw_group_counts(pyro_sw_group *g, int64_t *cas_tried, int64_t *cas_hooked)
+{
+    if (!g) return fail(PYRO_EINVAL, "group is NULL");
+    if (!cas_tried || !cas_hooked) return fail(PYRO_EINVAL, "outputs must not be NULL");
+    unsigned long long v[2] = {0, 0};
+    if (g->d_counts) {
+        HIP_OR_FAIL(&g->broken, hipStreamSynchronize(g->stream));
+        HIP_OR_FAIL(&g->broken, hipMemcpy(v, g->d_counts, sizeof(v), hipMemcpyDeviceToHost));
+    }
+    *cas_tried = (int64_t)v[0];
+    *cas_hooked = (int64_t)v[1];
+    return PYRO_OK;
+}
+
 int pyro_sw_group_get_mode(const pyro_sw_group *g, int *ising_mode, int *resident)
 {
     if (!g) return fail(PYRO_EINVAL, "group is NULL");
@@ -1652,6 +1688,7 @@ int pyro_sw_group_destroy(pyro_sw_group *g)
     g->timer.release();
     drop_slices(g);
     free_tables(g->res);
+    if (g->d_counts) hipFree(g->d_counts);
     if (g->res_stream) {
         hipStreamSynchronize(g->res_stream);
         hipStreamDestroy(g->res_stream);

@@ -156,6 +156,13 @@ struct TileIdx {
         c.lcell = in ? (tz * TY + ty) * TX + tx : -1;
         return c;
     }
+    // Global site index of the first site of local row `row` = lz TY + ly of
+    // the tile (its cells x = bx TX .. bx TX + TX - 1 are consecutive).
+    __device__ __forceinline__ int row_base(int row) const
+    {
+        const int lz = row / TY, ly = row % TY;
+        return 16 * (base + mul24(mul24(lz, L) + ly, L));
+    }
     // Global site index of local key l = 16 c + k.
     __device__ __forceinline__ int global_site(int l) const
     {
@@ -174,6 +181,21 @@ struct TileIdx {
         const int ly = small_div(rem, L, inv_L);
         const int lx = rem - mul24(ly, L);
         return 16 * ((lz * TY + ly) * TX + lx) + (site & 15);
+    }
+    // Local key of a site of this tile from the thread's own cell (global
+    // index `cell`, local index `lcell`): the cell offset dc = dz L^2 + dy L
+    // + dx has |dx| < TX, |dy| < TY, |dz| < TZ, so when L >= 2 max(TX, TY,
+    // TZ) (near_decodable) dz and dy are the nearest integers of dc / L^2 and
+    // of the remainder / L (each more than 0.03 away from a half-integer).
+    __device__ __forceinline__ bool near_decodable() const { return L >= 2 * (TX > TY ? (TX > TZ ? TX : TZ) : (TY > TZ ? TY : TZ)); }
+    __device__ __forceinline__ int local_key_near(int site, int cell, int lcell) const
+    {
+        const int dc = (site >> 4) - cell;
+        const int dz = (int)rintf((float)dc * inv_LL);
+        const int r1 = dc - __mul24(dz, L * L);
+        const int dy = (int)rintf((float)r1 * inv_L);
+        const int dx = r1 - __mul24(dy, L);
+        return 16 * (lcell + dx + dy * TX + dz * (TX * TY)) + (site & 15);
     }
     // The seven cells the bonds of cell (x, y, z) touch (periodic wrap).
     __device__ __forceinline__ void neighbours(int x, int y, int z, int cell, int lcell,
@@ -270,7 +292,8 @@ __device__ __forceinline__ int forest_find(int32_t *lab, int x)
 // first and, when it is larger than b, hooked under b by CAS without walking
 // b; otherwise b's root is walked and the larger of the two roots is hooked
 // under the smaller.  A lost CAS continues from the value it returned.
-__device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
+template <bool COUNT = false>
+__device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b, unsigned long long *counts)
 {
     for (int it = 0; it < kWalkCap; ++it) {
         a = forest_find(lab, a);
@@ -285,6 +308,10 @@ __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b)
             }
         }
         const int old = atomicCAS(lab + a, a, kTag | b);
+        if (COUNT) {  // measurement runs only (a kernel of its own)
+            atomicAdd(&counts[0], 1ull);
+            if (old == a) atomicAdd(&counts[1], 1ull);
+        }
         if (old == a) return;
         a = old & kIdxMask;
     }
@@ -337,8 +364,10 @@ __device__ __forceinline__ int canonical_label(const int32_t *label, int64_t i)
 // else r itself, whose coin is the tile's.  Only LDS is read.
 template <int NC, int TX, int TY, int TZ>
 __device__ __forceinline__ uint32_t cell_flip_mask(const int (&lab)[16], const int *LAB, const uint32_t *CB,
-                                                  const TileIdx<TX, TY, TZ> &ti, uint32_t t, PhiloxKey key)
+                                                  const TileIdx<TX, TY, TZ> &ti, int cell, int lcell, uint32_t t,
+                                                  PhiloxKey key)
 {
+    const bool near = ti.near_decodable();  // uniform
     int last_in = -1;
     uint32_t last_coin = 0, mask = 0;
 #pragma unroll
@@ -352,7 +381,7 @@ __device__ __forceinline__ uint32_t cell_flip_mask(const int (&lab)[16], const i
         } else if (r0 == last_in) {
             coin = last_coin;
         } else {
-            const int key16 = ti.local_key(r0);
+            const int key16 = near ? ti.local_key_near(r0, cell, lcell) : ti.local_key(r0);
             const int v = LAB[lds_pos<NC>(key16)];
             if (v < 0) coin = ((uint32_t)v >> 30) & 1u;
             else if (v & kTag) coin = cluster_coin(v & kIdxMask, t, key);  // as above
@@ -550,7 +579,12 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
     __syncthreads();
     // Tile-local roots of the thread's sites, as global site indices: into
     // the labels, and into the forest entries, where the emission below
-    // reads the root of any site of the tile.
+    // reads the root of any site of the tile.  A key's global index is the
+    // base of its row (a table in U, free after the unions) plus its offset
+    // in the row, 16 lx + k.
+    static_assert((TX & (TX - 1)) == 0 && TX * TY * TZ <= 1024, "power-of-two rows");
+    constexpr int kRowShift = 4 + (TX == 4 ? 2 : (TX == 8 ? 3 : 4));
+    for (int row = tid; row < TY * TZ; row += NC) U[row] = (uint32_t)ti.row_base(row);
     int r[16];
     if (valid) {
         const uint32_t base = node_off(16 * lcid);
@@ -562,7 +596,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         const uint32_t base = node_off(16 * lcid);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            r[k] = ti.global_site(r[k]);
+            r[k] = (int)U[(uint32_t)r[k] >> kRowShift] + (r[k] & (16 * TX - 1));
             node(P, base + 4 * k) = (uint32_t)r[k];
         }
         int4 *out = reinterpret_cast<int4 *>(d.label + 16 * cell);
@@ -693,8 +727,9 @@ struct UniteLds {
     int nroots, missed;
 };
 
-template <int NT>
-__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid, UniteLds &S)
+template <int NT, bool COUNT = false>
+__device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid, UniteLds &S,
+                                                 unsigned long long *counts)
 {
     constexpr int H = kTileRoots;                    // root slots
     constexpr int kMaxListed = UniteLds::kMaxListed;  // pairs kept in LDS
@@ -725,7 +760,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         const int ra = name_root(lab, p.x), rb = name_root(lab, p.y);
         const int sa = ra == rb ? -1 : insert(ra), sb = ra == rb ? -1 : insert(rb);
         const bool listed = k < kMaxListed && sa >= 0 && sb >= 0;
-        if (!listed && ra != rb) forest_unite(lab, ra, rb);
+        if (!listed && ra != rb) forest_unite<COUNT>(lab, ra, rb, counts);
         if (ra != rb && (sa < 0 || sb < 0)) S.missed = 1;
         if (k < kMaxListed) {
             S.PA[k] = (int16_t)(listed ? sa : -1);
@@ -784,7 +819,7 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         if (S.HK[s] < 0) continue;
         const int rs = (int)(S.BEST[slot_find(s)] & (uint64_t)(H - 1));
         if (!S.missed && with_reps) head[2 + H + S.PA[s]] = S.PA[rs];
-        if (rs != s) forest_unite(lab, S.HK[s], S.HK[rs]);
+        if (rs != s) forest_unite<COUNT>(lab, S.HK[s], S.HK[rs], counts);
     }
     if (tid == 0) head[1] = S.missed ? 0 : (with_reps ? -S.nroots : S.nroots);
 }
@@ -850,14 +885,17 @@ __device__ __forceinline__ void store_tile(const RepDesc &d, const RepState &st,
 }
 
 // Unite pass of one tile (NT threads).
-template <int NT>
-__device__ __forceinline__ void unite_tile(const RepDesc &d, int tile, int tid, UniteLds &S)
+template <int NT, bool COUNT = false>
+__device__ __forceinline__ void unite_tile(const RepDesc &d, int tile, int tid, UniteLds &S,
+                                           unsigned long long *counts = nullptr)
 {
     int *head = d.pairs + (int64_t)tile * d.list_stride;
-    unite_tile_pairs<NT>(d.label, head, head[0], d.list_stride, tid, S);
+    unite_tile_pairs<NT, COUNT>(d.label, head, head[0], d.list_stride, tid, S, counts);
 }
 
-template <int PASS>
+// PASS: kPassUnite or kPassStore; COUNT: the unite pass counts its
+// compare-and-swaps into c.counts (measurement runs).
+template <int PASS, bool COUNT = false>
 __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
 {
     __shared__ union {
@@ -869,7 +907,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
-    if (PASS == kPassUnite) unite_tile<kForestThreads>(d, tile, threadIdx.x, S.u);
+    if (PASS == kPassUnite) unite_tile<kForestThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts);
     else store_tile<kForestThreads>(d, st, tile, threadIdx.x, S.HK);
 }
 

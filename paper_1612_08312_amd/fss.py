@@ -357,7 +357,7 @@ def _scaled(temps, Ls, tc, nu, values, errs, power=0.0, lattice="pyro", d1=1.0, 
     return xs, ys, dys
 
 
-def fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice="pyro"):
+def fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice="pyro", order=None):
     """T_c and nu minimising the collapse quality of U (Eq. 3)."""
     from scipy.optimize import minimize
 
@@ -365,7 +365,7 @@ def fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice="pyro"):
         tc, nu = v
         if nu <= 0.05:
             return 1e30
-        return collapse_quality(*_scaled(temps, Ls, tc, nu, U, dU, lattice=lattice))
+        return collapse_quality(*_scaled(temps, Ls, tc, nu, U, dU, lattice=lattice), order=order)
 
     best = minimize(cost, x0=[tc0, nu0], method="Nelder-Mead",
                     options=dict(xatol=1e-7, fatol=1e-9, maxiter=4000,
@@ -373,31 +373,32 @@ def fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice="pyro"):
     return float(best.x[0]), float(best.x[1]), float(best.fun)
 
 
-def fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lo=0.2, hi=0.9, lattice="pyro"):
+def fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lo=0.2, hi=0.9, lattice="pyro", order=None):
     """beta/nu minimising the collapse quality of <m^2> (N^(1/3))^(2 beta/nu)
     at fixed T_c and nu (Eq. 4)."""
     from scipy.optimize import minimize_scalar
 
     def cost(bn):
-        return collapse_quality(*_scaled(temps, Ls, tc, nu, m2, dm2, power=2.0 * bn, lattice=lattice))
+        return collapse_quality(*_scaled(temps, Ls, tc, nu, m2, dm2, power=2.0 * bn, lattice=lattice), order=order)
 
     best = minimize_scalar(cost, bounds=(lo, hi), method="bounded", options=dict(xatol=1e-6))
     return float(best.x), float(best.fun)
 
 
-def analyse(temps, Ls, rm: np.ndarray, tc0: float, nu0: float, lattice="pyro"):
-    """Everything the paper extracts from one model's scan: U and <m^2>
-    tables, Binder crossings, T_c, nu, beta/nu (jackknife errors)."""
+def collapse_fit(temps, Ls, rm: np.ndarray, tc0: float, nu0: float, lattice="pyro", order=None):
+    """T_c, nu and beta/nu from the collapses of U and <m^2> with the given
+    interpolation order of the collapse measure, errors by the jackknife over
+    runs (the fits redone with one run left out)."""
     U, dU, m2, dm2 = estimates(rm)
-    tc, nu, q = fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice)
-    bn, qb = fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lattice=lattice)
+    tc, nu, q = fit_tc_nu(temps, Ls, U, dU, tc0, nu0, lattice, order)
+    bn, qb = fit_beta_nu(temps, Ls, m2, dm2, tc, nu, lattice=lattice, order=order)
     runs_first = np.moveaxis(rm, 2, 0)
 
     def refit(v):
         sub = np.moveaxis(v, 0, 2)
         u, du, mm, dmm = estimates(sub)
-        t, n, _ = fit_tc_nu(temps, Ls, u, du, tc, nu, lattice)
-        b, _ = fit_beta_nu(temps, Ls, mm, dmm, t, n, lattice=lattice)
+        t, n, _ = fit_tc_nu(temps, Ls, u, du, tc, nu, lattice, order)
+        b, _ = fit_beta_nu(temps, Ls, mm, dmm, t, n, lattice=lattice, order=order)
         return np.array([t, n, b])
 
     R = rm.shape[2]
@@ -406,12 +407,22 @@ def analyse(temps, Ls, rm: np.ndarray, tc0: float, nu0: float, lattice="pyro"):
         err = np.sqrt((R - 1) / R * np.sum((loo - loo.mean(axis=0)) ** 2, axis=0))
     else:
         err = np.full(3, np.nan)
-    return dict(
-        U=U.tolist(), dU=dU.tolist(), m2=m2.tolist(), dm2=dm2.tolist(),
-        crossings=[dict(L1=a, L2=b, T=t, dT=e) for (a, b, t, e) in crossings(temps, rm, Ls)],
-        Tc=tc, dTc=float(err[0]), nu=nu, dnu=float(err[1]), beta_over_nu=bn,
-        dbeta_over_nu=float(err[2]), quality_U=q, quality_m2=qb,
-    )
+    return dict(Tc=tc, dTc=float(err[0]), nu=nu, dnu=float(err[1]), beta_over_nu=bn, dbeta_over_nu=float(err[2]),
+                quality_U=q, quality_m2=qb)
+
+
+def analyse(temps, Ls, rm: np.ndarray, tc0: float, nu0: float, lattice="pyro"):
+    """Everything the paper extracts from one model's scan: U and <m^2>
+    tables, Binder crossings, T_c, nu, beta/nu (jackknife errors).  The
+    collapse fits are reported with the default three-point measure and,
+    side by side, with Houdayer and Hartmann's linear one (collapse_linear)."""
+    U, dU, m2, dm2 = estimates(rm)
+    res = dict(U=U.tolist(), dU=dU.tolist(), m2=m2.tolist(), dm2=dm2.tolist(),
+               crossings=[dict(L1=a, L2=b, T=t, dT=e) for (a, b, t, e) in crossings(temps, rm, Ls)])
+    res.update(collapse_fit(temps, Ls, rm, tc0, nu0, lattice, order=COLLAPSE_ORDER))
+    res["collapse_order"] = COLLAPSE_ORDER
+    res["collapse_linear"] = collapse_fit(temps, Ls, rm, tc0, nu0, lattice, order=1)
+    return res
 
 
 def universal_factors(pyro: dict, sc: dict, nu: float, bn: float):

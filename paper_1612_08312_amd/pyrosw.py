@@ -45,6 +45,7 @@ EXPORTS = (
     "pyro_sw_group_create", "pyro_sw_group_sweep", "pyro_sw_group_autotune",
     "pyro_sw_group_set_tile_shape", "pyro_sw_group_set_timing", "pyro_sw_group_kernel_times",
     "pyro_sw_group_destroy", "pyro_sw_group_set_slices", "pyro_sw_group_set_mode", "pyro_sw_group_get_mode",
+    "pyro_sw_group_set_counting", "pyro_sw_group_counts",
     "pyro_sw_server_create", "pyro_sw_server_job_bytes", "pyro_sw_server_submit", "pyro_sw_server_step",
     "pyro_sw_server_status", "pyro_sw_server_take", "pyro_sw_server_clock", "pyro_sw_server_destroy",
     "pyro_sw_philox_rate", "pyro_sw_sweep_static", "pyro_sw_atomic_rate",
@@ -127,6 +128,8 @@ def load_library():
     lib.pyro_sw_group_set_slices.argtypes = [vp, i32]
     lib.pyro_sw_group_set_mode.argtypes = [vp, i32, i32]
     lib.pyro_sw_group_get_mode.argtypes = [vp, P(i32), P(i32)]
+    lib.pyro_sw_group_set_counting.argtypes = [vp, i32]
+    lib.pyro_sw_group_counts.argtypes = [vp, P(i64), P(i64)]
     lib.pyro_sw_group_set_timing.argtypes = [vp, i32]
     lib.pyro_sw_group_kernel_times.argtypes = [vp, P(ctypes.c_char_p), P(i64), P(f64), i32, P(i32)]
     lib.pyro_sw_group_destroy.argtypes = [vp]
@@ -322,6 +325,17 @@ def pyro_sw_group_get_mode(g):
     m, r = ctypes.c_int(), ctypes.c_int()
     _check(load_library().pyro_sw_group_get_mode(g, ctypes.byref(m), ctypes.byref(r)), "pyro_sw_group_get_mode")
     return m.value, bool(r.value)
+
+
+def pyro_sw_group_set_counting(g, on: bool):
+    _check(load_library().pyro_sw_group_set_counting(g, int(bool(on))), "pyro_sw_group_set_counting")
+
+
+def pyro_sw_group_counts(g):
+    """(compare-and-swaps the unite pass tried, those that hooked a root)."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().pyro_sw_group_counts(g, ctypes.byref(a), ctypes.byref(b)), "pyro_sw_group_counts")
+    return a.value, b.value
 
 
 def pyro_sw_group_destroy(g):

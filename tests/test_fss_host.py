@@ -98,6 +98,11 @@ def test_collapse_fit_recovers_the_scaling_parameters():
     assert res["quality_U"] < 5.0
     for c in res["crossings"]:
         assert abs(c["T"] - tc) < max(5 * c["dT"], 1e-5)
+    # the linear measure is reported beside the default one, with its own errors
+    lin = res["collapse_linear"]
+    assert res["collapse_order"] == 2
+    assert set(lin) == {"Tc", "dTc", "nu", "dnu", "beta_over_nu", "dbeta_over_nu", "quality_U", "quality_m2"}
+    assert abs(lin["Tc"] - tc) < max(6 * lin["dTc"], 5e-6)
 
 
 def test_fit_detects_a_wrong_starting_point():
