@@ -265,9 +265,12 @@ def serving_vs_plain(n_jobs, budget_gb, quantum_ms, dev):
     srv = pyrosw.Server(hbm_budget=int(budget_gb * (1 << 30)), max_running=64, quantum_ms=quantum_ms)
     results, summary = serving.run_stream(srv, jobs)
     srv.close()
+    log(f"bench: served {len(jobs)} jobs in {summary['makespan_s']:.1f} s; running them plain")
 
     durations, identical, mismatches = [], True, []
-    for r in results:
+    for idx, r in enumerate(results):
+        if idx and idx % 25 == 0:
+            log(f"bench: {idx} plain jobs done")
         j = r["job"]
         lt = pyrosw.Lattice(L=j["L"], model=j["model"], T=j["T"], J=j["J"], seed=j["seed"], start=j["start"],
                             device=dev)
@@ -419,11 +422,11 @@ def graph_throughput(sweeps, stream, dev):
 def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs, counters_valid):
     """Each Ising pass of one L=128 lattice (per-sweep launches, mean over the
     probe): its duration, what bounds it, and the fraction of that bound it
-    reaches.  The tile pass is bound by VALU issue (wave instructions per
-    launch from the counters / duration, against one wave instruction per CU
-    and cycle); the unite pass by device atomics (compare-and-swaps per launch
-    / duration, against the measured random compare-and-swap rate); the flip
-    by HBM (algorithmic bytes / duration); the store pass by forest walks and
+    reaches.  The tile pass and the flip are bound by VALU issue (wave
+    instructions per launch from the counters / duration, against one wave
+    instruction per CU and cycle); the unite pass by device atomics
+    (compare-and-swaps per launch / duration, against the measured random
+    compare-and-swap rate); the store pass by forest walks and
     scattered stores (counter bytes / duration, against the measured copy
     bandwidth); the finalize by launch latency (one workgroup per lattice)."""
     out = {}
@@ -445,8 +448,13 @@ def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs
                        hooks_per_launch=round(hooks_per_launch), achieved_cas_per_s=cas_per_launch / (us * 1e-6),
                        peak_cas_per_s=cas_ceiling, frac=cas_per_launch / (us * 1e-6) / cas_ceiling)
         elif k == "flip":
-            row.update(bound="hbm", alg_bytes_per_site=6.0, achieved_GBps=6.0 * N / (us * 1e-6) / 1e9,
-                       peak_GBps=HBM_PEAK_GBS, frac=6.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9))
+            row["bound"] = "VALU issue"
+            if counters_valid and k in MEASURED_ISSUE:
+                valu, salu, waves = MEASURED_ISSUE[k]
+                row.update(valu_per_wave=round(valu / waves), salu_per_wave=round(salu / waves),
+                           achieved_wave_instr_per_s=valu / (us * 1e-6), peak_wave_instr_per_s=VALU_ISSUE_PEAK,
+                           frac=valu / (us * 1e-6) / VALU_ISSUE_PEAK)
+            row.update(alg_bytes_per_site=6.0, hbm_alg_frac=6.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9))
         elif k == "canon_store":
             row["bound"] = "forest walks and scattered 4-byte stores"
             if counters_valid and k in MEASURED_TRAFFIC:
