@@ -46,8 +46,8 @@ struct IsingTileLds {
 
 template <int TX, int TY, int TZ>
 struct IsingFlipLds {
-    int LAB[16 * TX * TY * TZ];  // labels of the tile's sites
-    uint32_t CB[TX * TY * TZ];   // coins of the tile's sites
+    alignas(16) int LAB[16 * TX * TY * TZ];  // labels of the tile's sites
+    alignas(16) uint32_t CB[TX * TY * TZ];   // coins of the tile's sites
     int64_t red[16];
 };
 
@@ -126,6 +126,30 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     ising_tile_pass<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
 }
 
+// XOR flip of the int8 spins of `cell` selected by `flipmask` (bit k = site
+// 16 cell + k); returns the magnetisation of the cell's new state.
+__device__ __forceinline__ int flip_cell(void *spins, int cell, uint32_t flipmask)
+{
+    int4 *S4 = reinterpret_cast<int4 *>(spins);
+    const int4 sv = S4[cell];
+    uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
+    int down = 0, occupied = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t f4 = (flipmask >> (4 * q)) & 15u;
+        // +1 (0x01) <-> -1 (0xFF) is XOR 0xFE on the flipped bytes; a
+        // vacant site (0x00) is left alone
+        const uint32_t nz = (((w[q] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w[q]) & 0x80808080u;
+        const uint32_t fx = (((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
+                             ((f4 >> 3 & 1u) * 0xFE000000u)) & ((nz >> 7) * 0xFEu);
+        w[q] ^= fx;
+        down += (int)__popc(w[q] & 0x80808080u);
+        occupied += (int)__popc(nz);
+    }
+    S4[cell] = make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
+    return occupied - 2 * down;
+}
+
 // One workgroup per tile: the labels of the tile's sites and the coins of
 // its own clusters are staged in LDS, so the coin of every site's cluster
 // (site -> local root -> stored encoding or the root's own coin) costs no
@@ -161,28 +185,40 @@ __device__ __forceinline__ void ising_flip_pass(const RepDesc &d, const RepState
     CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
     __syncthreads();
     int mag = 0;
-    if (valid) {
-        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
-        int4 *S4 = reinterpret_cast<int4 *>(d.spins);
-        const int4 sv = S4[cell];
-        uint32_t w[4] = {(uint32_t)sv.x, (uint32_t)sv.y, (uint32_t)sv.z, (uint32_t)sv.w};
-        int down = 0, occupied = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t f4 = (flipmask >> (4 * q)) & 15u;
-            // +1 (0x01) <-> -1 (0xFF) is XOR 0xFE on the flipped bytes; a
-            // vacant site (0x00) is left alone
-            const uint32_t nz = (((w[q] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w[q]) & 0x80808080u;
-            const uint32_t fx = (((f4 & 1u) * 0xFEu) | ((f4 >> 1 & 1u) * 0xFE00u) | ((f4 >> 2 & 1u) * 0xFE0000u) |
-                                 ((f4 >> 3 & 1u) * 0xFE000000u)) & ((nz >> 7) * 0xFEu);
-            w[q] ^= fx;
-            down += (int)__popc(w[q] & 0x80808080u);
-            occupied += (int)__popc(nz);
-        }
-        S4[cell] = make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
-        mag = occupied - 2 * down;
-    }
+    if (valid) mag = flip_cell(d.spins, cell, cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key));
     const int64_t msum = block_sum<int64_t>((int64_t)mag, red);
+    if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
+}
+
+// The flip pass for an aligned tiling (d.lgL >= 0, TX >= 8; see
+// aligned_local_key): every thread's cell lies in the lattice, the labels
+// are staged by local key with 16-byte stores, the tile's coin words are
+// drawn once per FLIP block by NC / 8 threads, and each site's coin is found
+// without division or branch.  Results equal ising_flip_pass.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void ising_flip_pass_aligned(const RepDesc &d, const RepState &st, int tile, int tid,
+                                                        IsingFlipLds<TX, TY, TZ> &S)
+{
+    constexpr int NC = TX * TY * TZ;
+    const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int cell = cell_index(ti.bx * TX + lx, ti.by * TY + ly, ti.bz * TZ + lz, d.L);
+    int lab[16];
+    const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
+    int4 *LAB4 = reinterpret_cast<int4 *>(S.LAB) + 4 * tid;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int4 v = L4[q];
+        LAB4[q] = v;
+        lab[4 * q] = v.x;
+        lab[4 * q + 1] = v.y;
+        lab[4 * q + 2] = v.z;
+        lab[4 * q + 3] = v.w;
+    }
+    if (tid < NC / 8) reinterpret_cast<uint4 *>(S.CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
+    __syncthreads();
+    const int mag = flip_cell(d.spins, cell, cell_flip_mask_aligned<TX, TY, TZ>(lab, S.LAB, S.CB, d.lgL));
+    const int64_t msum = block_sum<int64_t>((int64_t)mag, S.red);
     if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
 }
 
@@ -194,6 +230,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
+    if constexpr (TX % 8 == 0) {
+        if (d.lgL >= 0) {
+            ising_flip_pass_aligned<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+            return;
+        }
+    }
     ising_flip_pass<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
 }
 

@@ -46,6 +46,7 @@ inline TileDims tile_dims(int shape)
 struct RepDesc {
     // geometry
     int L, ntx, nty, ntz;  // tiles per axis for the chain's tile shape
+    int lgL;               // log2 L when L is a power of two that every tile edge divides, else -1
     int64_t ncell, N;
     // device buffers owned by the replica
     void *spins;       // int8 [N] or float [n][N]

@@ -196,8 +196,8 @@ template <int NV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
-    __shared__ int LAB[16 * NC];
-    __shared__ uint32_t CB[NC];
+    __shared__ __align__(16) int LAB[16 * NC];
+    __shared__ __align__(16) uint32_t CB[NC];
     __shared__ double red[16];
     const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
@@ -213,6 +213,10 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
     const int cell = cell_index(x, y, z, L);
     const int64_t N = d.N;
     float *s = (float *)d.spins;
+    // An aligned tiling (TX >= 8) stages the labels by local key and draws
+    // the coin words once per FLIP block (as the aligned Ising flip does).
+    bool aligned = false;
+    if constexpr (TX % 8 == 0) aligned = d.lgL >= 0;  // uniform
     int lab[16];
     if (valid) {
         const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
@@ -223,11 +227,18 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
             lab[4 * q + 1] = v.y;
             lab[4 * q + 2] = v.z;
             lab[4 * q + 3] = v.w;
+            if (aligned) reinterpret_cast<int4 *>(LAB)[4 * tid + q] = v;
         }
+        if (!aligned) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
+            for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
+        }
     }
-    CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
+    if constexpr (TX % 8 == 0) {
+        if (aligned && tid < NC / 8)
+            reinterpret_cast<uint4 *>(CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
+    }
+    if (!aligned) CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
     __syncthreads();
     double M[NV];
 #pragma unroll
@@ -236,7 +247,13 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
         float r[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
-        const uint32_t flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
+        uint32_t flipmask;
+        if constexpr (TX % 8 == 0) {
+            flipmask = aligned ? cell_flip_mask_aligned<TX, TY, TZ>(lab, LAB, CB, d.lgL)
+                               : cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
+        } else {
+            flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
+        }
         float v[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {

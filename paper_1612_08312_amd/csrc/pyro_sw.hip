@@ -408,6 +408,10 @@ RepDesc lattice_desc(int L, int model, double J, uint64_t seed, uint32_t thr_hi,
     d.ntx = (L + t.x - 1) / t.x;
     d.nty = (L + t.y - 1) / t.y;
     d.ntz = (L + t.z - 1) / t.z;
+    d.lgL = -1;
+    if ((L & (L - 1)) == 0 && L % t.x == 0 && L % t.y == 0 && L % t.z == 0)
+        for (int v = L, k = 0; v > 0; v >>= 1, ++k)
+            if (v == 1) d.lgL = k;
     d.ncell = (int64_t)L * L * L;
     d.N = 16 * d.ncell;
     d.spins = spins;

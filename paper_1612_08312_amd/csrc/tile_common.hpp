@@ -394,6 +394,61 @@ __device__ __forceinline__ uint32_t cell_flip_mask(const int (&lab)[16], const i
     return mask;
 }
 
+constexpr int const_log2(int v) { return v <= 1 ? 0 : 1 + const_log2(v >> 1); }
+
+// Aligned tiling: the lattice edge is L = 2^lg and every tile edge divides
+// it, so each tile starts at a multiple of its edges and a site index
+// 16 (x + L y + L^2 z) + k of the tile has its local cell coordinates in
+// fixed bit fields.  The local key 16 (lx + TX ly + TX TY lz) + k is then
+// a few bit-field extracts, whatever value is decoded (an encoding yields
+// some key of the tile, never one outside it).
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ int aligned_local_key(int site, int lg)
+{
+    constexpr int lTX = const_log2(TX), lTY = const_log2(TY);
+    const uint32_t u = (uint32_t)site;
+    const uint32_t ly = __builtin_amdgcn_ubfe(u, (uint32_t)(4 + lg), (uint32_t)const_log2(TY));
+    const uint32_t lz = __builtin_amdgcn_ubfe(u, (uint32_t)(4 + 2 * lg), (uint32_t)const_log2(TZ));
+    return (int)((u & (16u * TX - 1u)) | (ly << (4 + lTX)) | (lz << (4 + lTX + lTY)));
+}
+
+// Flip mask of a flip kernel's cell for an aligned tiling (see
+// aligned_local_key).  LAB holds the tile's labels by local key; CB holds
+// the coin words of the tile's cells, two cells per word as the flip stream
+// draws them (bit (key & 31) of word key >> 5 is the coin of local key
+// `key`).  The same rule as cell_flip_mask: a stored encoding, in the site's
+// own entry or in its local root's, gives the coin; otherwise the local
+// root's own coin.  No branch: both LDS words are read for every site.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ uint32_t cell_flip_mask_aligned(const int (&lab)[16], const int *LAB, const uint32_t *CB,
+                                                          int lg)
+{
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int r = lab[k];
+        const int key = aligned_local_key<TX, TY, TZ>(r, lg);
+        const int u = r < 0 ? r : LAB[key];
+        const bool enc = u < 0;
+        const uint32_t word = enc ? (uint32_t)u : CB[key >> 5];
+        mask |= __builtin_amdgcn_ubfe(word, enc ? 30u : (uint32_t)key & 31u, 1u) << k;
+    }
+    return mask;
+}
+
+// Coin words of an aligned tile (NC / 8 threads, thread j): local cells
+// 8j .. 8j + 7 are eight consecutive cells of one x row starting at a
+// multiple of 8 (TX >= 8), i.e. exactly the cells of one FLIP block, whose
+// four words cover two cells each (cell_coins).
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ uint4 aligned_coin_words(const TileIdx<TX, TY, TZ> &ti, int j, uint32_t t, PhiloxKey key)
+{
+    static_assert(TX % 8 == 0, "a FLIP block is 8 cells of one x row");
+    const int c0 = 8 * j;
+    const int gcell = cell_index(ti.bx * TX + c0 % TX, ti.by * TY + (c0 / TX) % TY, ti.bz * TZ + c0 / (TX * TY), ti.L);
+    return philox4x32_10((uint32_t)gcell >> 3, t, kStreamFlip, 0u, key);
+}
+
 // Site `site` of the neighbour cell `code` (lattice.hpp codes) of the cell
 // at (x, y, z); xm, ym, zm are the wrapped lower coordinates.  Bit 0/1/2 of
 // the 3-bit field of a code says whether the neighbour is one cell lower in
@@ -708,7 +763,9 @@ enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 // hooked under, and its entry (itself) is already its canonical form.
 constexpr int kTileRoots = 1024;  // LDS root table of the unite pass
 
-constexpr int kForestThreads = 512;  // threads per tile in the unite and store passes
+constexpr int kForestThreads = 512;  // threads per tile in the store pass
+constexpr int kUniteThreads = 256;   // threads per tile in the unite pass (its CAS chains are latency bound;
+                                     // smaller workgroups let more tiles run at once)
 
 // LDS words that other threads of the workgroup change concurrently (root
 // tables and parent slots of the unite and store passes) are read and
@@ -896,7 +953,7 @@ __device__ __forceinline__ void unite_tile(const RepDesc &d, int tile, int tid, 
 // PASS: kPassUnite or kPassStore; COUNT: the unite pass counts its
 // compare-and-swaps into c.counts (measurement runs).
 template <int PASS, bool COUNT = false>
-__global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
+__global__ __launch_bounds__(PASS == kPassUnite ? kUniteThreads : kForestThreads) void k_forest(Chain c)
 {
     __shared__ union {
         UniteLds u;
@@ -907,7 +964,7 @@ __global__ __launch_bounds__(kForestThreads) void k_forest(Chain c)
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
-    if (PASS == kPassUnite) unite_tile<kForestThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts);
+    if (PASS == kPassUnite) unite_tile<kUniteThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts);
     else store_tile<kForestThreads>(d, st, tile, threadIdx.x, S.HK);
 }
 
