@@ -42,8 +42,8 @@ def bytes_per_site(shape):
     return {
         "local": 1.0 + 4.0,            # read spins, write tile-local roots
         "unite": 0.0,                  # forest walks over the crossing lists (data dependent)
-        "canon_store": 0.0,            # idem
-        "flip": 4.0 + 1.0 + 1.0,       # read labels, read and write spins (coins are drawn in the kernel)
+        "canon_store": 0.0,            # idem (O(n) chains; the Ising flip settles its own roots)
+        "flip": 4.0 + 1.0 + 1.0,       # read labels, read and write spins (root settling walks and coins not counted)
         "persist": 11.0,               # the whole sweep (every pass), per sweep of each lattice
         "energy": 1.0,                 # read spins
         "finalize": 0.0,
@@ -426,9 +426,10 @@ def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs
     instructions per launch from the counters / duration, against one wave
     instruction per CU and cycle); the unite pass by device atomics
     (compare-and-swaps per launch / duration, against the measured random
-    compare-and-swap rate); the store pass by forest walks and
-    scattered stores (counter bytes / duration, against the measured copy
-    bandwidth); the finalize by launch latency (one workgroup per lattice)."""
+    compare-and-swap rate); the finalize by launch latency (one workgroup
+    per lattice).  The Ising chain has no store pass: each tile settles its
+    own hooked roots at the start of its flip (a store row appears only for
+    chains that run one)."""
     out = {}
     for k, (n, ms) in kt.items():
         if not n:

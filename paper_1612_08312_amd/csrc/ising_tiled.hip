@@ -10,13 +10,15 @@
 //                  write every site's tile-local root as a global site index
 //                  and list the tile's crossing pairs (tile_components).  The
 //                  parallel-bond count is the energy of the incoming state.
-//   k_forest       unite and store passes over the crossing lists
-//                  (tile_common.hpp); the store pass writes each merged
-//                  cluster's smallest site and flip coin into its local roots.
-//   k_flip_ising   one workgroup per tile: the coin of every site's cluster
-//                  from an LDS copy of the tile's labels and the tile's own
-//                  coins, XOR flip of the int8 spins, magnetisation of the new
-//                  state.
+//   k_forest      unite pass over the crossing lists (tile_common.hpp): the
+//                  global forest over the tiles' local roots.
+//   k_settle_flip_ising  one workgroup per tile: settle the tile's hooked
+//                  local roots (their cluster's smallest site and flip
+//                  coin), then the coin of every site's cluster from an LDS
+//                  copy of the tile's labels and the tile's own coins, XOR
+//                  flip of the int8 spins, magnetisation of the new state.
+//                  (The persistent kernel runs the store pass of
+//                  tile_common.hpp and ising_flip_pass instead.)
 //   k_finalize_ising  fixed-order sums of the partials into the records,
 //                  then advance the replica's state.
 // Local site order inside a tile follows the global order, so a tile-local
@@ -190,53 +192,139 @@ __device__ __forceinline__ void ising_flip_pass(const RepDesc &d, const RepState
     if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
 }
 
-// The flip pass for an aligned tiling (d.lgL >= 0, TX >= 8; see
-// aligned_local_key): every thread's cell lies in the lattice, the labels
-// are staged by local key with 16-byte stores, the tile's coin words are
-// drawn once per FLIP block by NC / 8 threads, and each site's coin is found
-// without division or branch.  Results equal ising_flip_pass.
+// LDS of the settle-and-flip pass: the flip's, plus the list of the tile's
+// hooked local roots.
 template <int TX, int TY, int TZ>
-__device__ __forceinline__ void ising_flip_pass_aligned(const RepDesc &d, const RepState &st, int tile, int tid,
-                                                        IsingFlipLds<TX, TY, TZ> &S)
+struct IsingSettleLds {
+    IsingFlipLds<TX, TY, TZ> f;
+    uint16_t HL[4 * TX * TY * TZ];  // local keys of hooked local roots (unbounded count: the rest settle in place)
+    int wtot[TX * TY * TZ / 64];
+};
+
+// Settle and flip, one workgroup per tile, once every unite is done.  The
+// tile settles its own hooked local roots (entry kTag | p): the walk from p
+// ends at the cluster's tree root, its smallest site, or at an encoding
+// that another settle wrote on the way, and the root's entry becomes the
+// stored encoding (smallest site and coin) in the label array (for later
+// walks and the host's labels) and in the LDS copy of the tile's labels.
+// A local root that is a tree root keeps its own index: its coin is the
+// tile's own coin of that site.  Every local root is settled by its own
+// tile, so no other workgroup writes an entry this one reads from LDS.  The
+// flip then follows ising_flip_pass (ALIGNED = false), or for an aligned
+// tiling (d.lgL >= 0, TX >= 8; see aligned_local_key) stages the labels by
+// local key with 16-byte stores, draws the coin words once per FLIP block
+// and finds each site's coin without division or branch (ALIGNED = true);
+// a hooked site reads its own settled entry.
+template <int TX, int TY, int TZ, bool ALIGNED>
+__device__ __forceinline__ void ising_settle_flip_pass(const RepDesc &d, const RepState &st, int tile, int tid,
+                                                       IsingSettleLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
+    constexpr int kCapHL = 4 * NC;
+    int *LAB = S.f.LAB;
+    uint32_t *CB = S.f.CB;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
+    const int L = d.L;
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    const int cell = cell_index(ti.bx * TX + lx, ti.by * TY + ly, ti.bz * TZ + lz, d.L);
+    const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
+    const bool valid = ALIGNED || (x < L && y < L && z < L);
+    const int cell = cell_index(x, y, z, L);
+    auto pos = [](int key) { return ALIGNED ? key : lds_pos<NC>(key); };
     int lab[16];
-    const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
-    int4 *LAB4 = reinterpret_cast<int4 *>(S.LAB) + 4 * tid;
+    uint32_t hm = 0;  // bit k: site k of the cell is a hooked local root
+    if (valid) {
+        const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int4 v = L4[q];
-        LAB4[q] = v;
-        lab[4 * q] = v.x;
-        lab[4 * q + 1] = v.y;
-        lab[4 * q + 2] = v.z;
-        lab[4 * q + 3] = v.w;
+        for (int q = 0; q < 4; ++q) {
+            const int4 v = L4[q];
+            if (ALIGNED) reinterpret_cast<int4 *>(LAB)[4 * tid + q] = v;
+            lab[4 * q] = v.x;
+            lab[4 * q + 1] = v.y;
+            lab[4 * q + 2] = v.z;
+            lab[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (!ALIGNED) LAB[k * NC + tid] = lab[k];
+            const bool hooked = ((uint32_t)lab[k] >> 30) == 1u;  // kTag | p
+            hm |= (uint32_t)hooked << k;
+            lab[k] = hooked ? 16 * cell + k : lab[k];  // the flip reads the settled entry of the site itself
+        }
     }
-    if (tid < NC / 8) reinterpret_cast<uint4 *>(S.CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
+    if constexpr (ALIGNED) {
+        if (tid < NC / 8) reinterpret_cast<uint4 *>(CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
+    } else {
+        CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
+    }
+    // List places of the thread's hooked roots: after those of the lanes
+    // below it (five ballots of its 0..16 count) and of the lower waves.
+    const uint32_t cnt = (uint32_t)__popc(hm);
+    uint32_t below = 0, wt = 0;
+#pragma unroll
+    for (int bit = 0; bit < 5; ++bit) {
+        const uint64_t b = __ballot((cnt >> bit) & 1u);
+        below += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u)) << bit;
+        wt += (uint32_t)__popcll(b) << bit;
+    }
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) S.wtot[wave] = (int)wt;
     __syncthreads();
-    const int mag = flip_cell(d.spins, cell, cell_flip_mask_aligned<TX, TY, TZ>(lab, S.LAB, S.CB, d.lgL));
-    const int64_t msum = block_sum<int64_t>((int64_t)mag, S.red);
+    int at = (int)below, nh = 0;
+    for (int w = 0; w < NC / 64; ++w) {
+        const int t = S.wtot[w];
+        at += w < wave ? t : 0;
+        nh += t;
+    }
+    if (hm) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (!((hm >> k) & 1u)) continue;
+            const int key = 16 * tid + k;
+            if (at < kCapHL) {
+                S.HL[at] = (uint16_t)key;
+            } else {  // beyond the list: settled by the thread that found it
+                const int e = canon_encoding(d.label, LAB[pos(key)] & kIdxMask, st.t, d.key);
+                lab_store(d.label, 16 * cell + k, e);
+                LAB[pos(key)] = e;
+            }
+            ++at;
+        }
+    }
+    __syncthreads();
+    const int nl = min(nh, kCapHL);
+    for (int j = tid; j < nl; j += NC) {
+        const int key = S.HL[j];
+        const int e = canon_encoding(d.label, LAB[pos(key)] & kIdxMask, st.t, d.key);
+        lab_store(d.label, ti.global_site(key), e);
+        LAB[pos(key)] = e;
+    }
+    __syncthreads();
+    int mag = 0;
+    if (valid) {
+        uint32_t flipmask;
+        if constexpr (ALIGNED) flipmask = cell_flip_mask_aligned<TX, TY, TZ>(lab, LAB, CB, d.lgL);
+        else flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
+        mag = flip_cell(d.spins, cell, flipmask);
+    }
+    const int64_t msum = block_sum<int64_t>((int64_t)mag, S.f.red);
     if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
 }
 
 template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX *TY *TZ) void k_flip_ising(Chain c)
+__global__ __launch_bounds__(TX *TY *TZ) void k_settle_flip_ising(Chain c)
 {
-    __shared__ IsingFlipLds<TX, TY, TZ> S;
+    __shared__ IsingSettleLds<TX, TY, TZ> S;
     const int rep = c.tile_rep[blockIdx.x];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     if constexpr (TX % 8 == 0) {
         if (d.lgL >= 0) {
-            ising_flip_pass_aligned<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+            ising_settle_flip_pass<TX, TY, TZ, true>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
             return;
         }
     }
-    ising_flip_pass<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+    ising_settle_flip_pass<TX, TY, TZ, false>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
 }
 
 // Records and state: energy partials (state before this sweep) into the
@@ -355,7 +443,7 @@ struct IsingFlip {
     template <int TX, int TY, int TZ>
     static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
     {
-        PYRO_LAUNCH(kKFlip, (k_flip_ising<TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        PYRO_LAUNCH(kKFlip, (k_settle_flip_ising<TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
         return hipSuccess;
     }
 };
@@ -363,7 +451,7 @@ struct IsingFlip {
 hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
     hipError_t e = with_tile_shape<IsingLocal>(c.shape, c, st, hook);
-    if (e == hipSuccess) e = launch_merge(c, st, hook);
+    if (e == hipSuccess) e = launch_unite(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<IsingFlip>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
     PYRO_LAUNCH(kKFinalize, k_finalize_ising, c.nreps, kFinalizeThreads, c);

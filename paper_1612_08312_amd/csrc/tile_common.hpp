@@ -752,8 +752,9 @@ enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 // then target distinct roots.  Pairs beyond the LDS tables are united
 // directly.
 //
-// The tile's list is then replaced by its distinct local roots, which is all
-// the store pass needs: it skips resolving names again.  With room for it
+// When a store pass follows (keep_roots), the tile's list is then replaced
+// by its distinct local roots, which is all the store pass needs: it skips
+// resolving names again.  With room for it
 // (list_stride >= 2 + 2 H), head[1] = -m and the m roots from head[2] on are
 // followed, from head[2 + H] on, by the list position of each root's group
 // representative, so the store pass walks once per group.  Otherwise
@@ -786,7 +787,7 @@ struct UniteLds {
 
 template <int NT, bool COUNT = false>
 __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n, int list_stride, int tid, UniteLds &S,
-                                                 unsigned long long *counts)
+                                                 unsigned long long *counts, bool keep_roots)
 {
     constexpr int H = kTileRoots;                    // root slots
     constexpr int kMaxListed = UniteLds::kMaxListed;  // pairs kept in LDS
@@ -812,16 +813,30 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         }
         return -1;
     };
-    for (int k = tid; k < n; k += NT) {
-        const int2 p = list[k];
-        const int ra = name_root(lab, p.x), rb = name_root(lab, p.y);
-        const int sa = ra == rb ? -1 : insert(ra), sb = ra == rb ? -1 : insert(rb);
-        const bool listed = k < kMaxListed && sa >= 0 && sb >= 0;
-        if (!listed && ra != rb) forest_unite<COUNT>(lab, ra, rb, counts);
-        if (ra != rb && (sa < 0 || sb < 0)) S.missed = 1;
-        if (k < kMaxListed) {
-            S.PA[k] = (int16_t)(listed ? sa : -1);
-            S.PB[k] = (int16_t)(listed ? sb : -1);
+    // Four of the thread's pairs at a time: their names are resolved with all
+    // label loads in flight together, then entered in the table.
+    constexpr int kBatch = 4;
+    for (int k0 = tid; k0 < n; k0 += kBatch * NT) {
+        int ra[kBatch], rb[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int k = k0 + i * NT;
+            const int2 p = k < n ? list[k] : make_int2(kTag, kTag);
+            ra[i] = name_root(lab, p.x);
+            rb[i] = name_root(lab, p.y);
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int k = k0 + i * NT;
+            if (k >= n) break;
+            const int sa = ra[i] == rb[i] ? -1 : insert(ra[i]), sb = ra[i] == rb[i] ? -1 : insert(rb[i]);
+            const bool listed = k < kMaxListed && sa >= 0 && sb >= 0;
+            if (!listed && ra[i] != rb[i]) forest_unite<COUNT>(lab, ra[i], rb[i], counts);
+            if (ra[i] != rb[i] && (sa < 0 || sb < 0)) S.missed = 1;
+            if (k < kMaxListed) {
+                S.PA[k] = (int16_t)(listed ? sa : -1);
+                S.PB[k] = (int16_t)(listed ? sb : -1);
+            }
         }
     }
     __syncthreads();
@@ -862,8 +877,8 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     // The pairs are read: overwrite them with the distinct local roots (at
     // most 2n of them, so they fit where the pairs were); PA now holds each
     // slot's list position.
-    const bool with_reps = list_stride >= 2 + 2 * H;
-    if (!S.missed) {
+    const bool with_reps = keep_roots && list_stride >= 2 + 2 * H;
+    if (keep_roots && !S.missed) {
         for (int s = tid; s < H; s += NT) {
             if (S.HK[s] < 0) continue;
             const int j = atomicAdd(&S.nroots, 1);
@@ -872,13 +887,43 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
         }
     }
     __syncthreads();
-    for (int s = tid; s < H; s += NT) {
-        if (S.HK[s] < 0) continue;
-        const int rs = (int)(S.BEST[slot_find(s)] & (uint64_t)(H - 1));
-        if (!S.missed && with_reps) head[2 + H + S.PA[s]] = S.PA[rs];
-        if (rs != s) forest_unite<COUNT>(lab, S.HK[s], S.HK[rs], counts);
+    // Each member of a group other than its smallest is hooked under the
+    // smallest (a smaller node, so a valid parent for a root).  A member that
+    // is still a root of the global forest is hooked by one compare-and-swap,
+    // without a walk, and the thread's compare-and-swaps are in flight
+    // together; one that finds the member already hooked continues the union
+    // from the parent it returned.
+    constexpr int kSlotsPerThread = (H + NT - 1) / NT;
+    constexpr int kHookBatch = kSlotsPerThread < 4 ? kSlotsPerThread : 4;
+    for (int i0 = 0; i0 < kSlotsPerThread; i0 += kHookBatch) {
+        int ha[kHookBatch], hb[kHookBatch], old[kHookBatch];
+#pragma unroll
+        for (int i = 0; i < kHookBatch; ++i) {
+            const int s = tid + (i0 + i) * NT;
+            ha[i] = -1;
+            hb[i] = -1;
+            if (s < H && S.HK[s] >= 0) {
+                const int rs = (int)(S.BEST[slot_find(s)] & (uint64_t)(H - 1));
+                if (!S.missed && with_reps) head[2 + H + S.PA[s]] = S.PA[rs];
+                if (rs != s) {
+                    ha[i] = S.HK[s];
+                    hb[i] = S.HK[rs];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kHookBatch; ++i) old[i] = ha[i] >= 0 ? atomicCAS(lab + ha[i], ha[i], kTag | hb[i]) : -1;
+#pragma unroll
+        for (int i = 0; i < kHookBatch; ++i) {
+            if (ha[i] < 0) continue;
+            if (COUNT) {  // measurement runs only (a kernel of its own)
+                atomicAdd(&counts[0], 1ull);
+                if (old[i] == ha[i]) atomicAdd(&counts[1], 1ull);
+            }
+            if (old[i] != ha[i]) forest_unite<COUNT>(lab, old[i] & kIdxMask, hb[i], counts);
+        }
     }
-    if (tid == 0) head[1] = S.missed ? 0 : (with_reps ? -S.nroots : S.nroots);
+    if (tid == 0 && keep_roots) head[1] = S.missed ? 0 : (with_reps ? -S.nroots : S.nroots);
 }
 
 // Store pass of one tile (NT threads; HK: kTileRoots ints of LDS).
@@ -944,10 +989,10 @@ __device__ __forceinline__ void store_tile(const RepDesc &d, const RepState &st,
 // Unite pass of one tile (NT threads).
 template <int NT, bool COUNT = false>
 __device__ __forceinline__ void unite_tile(const RepDesc &d, int tile, int tid, UniteLds &S,
-                                           unsigned long long *counts = nullptr)
+                                           unsigned long long *counts = nullptr, bool keep_roots = true)
 {
     int *head = d.pairs + (int64_t)tile * d.list_stride;
-    unite_tile_pairs<NT, COUNT>(d.label, head, head[0], d.list_stride, tid, S, counts);
+    unite_tile_pairs<NT, COUNT>(d.label, head, head[0], d.list_stride, tid, S, counts, keep_roots);
 }
 
 // PASS: kPassUnite or kPassStore; COUNT: the unite pass counts its
@@ -964,7 +1009,9 @@ __global__ __launch_bounds__(PASS == kPassUnite ? kUniteThreads : kForestThreads
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int tile = blockIdx.x - d.tile_base;
-    if (PASS == kPassUnite) unite_tile<kUniteThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts);
+    // The Ising chain settles its roots in the flip pass and runs no store
+    // pass, so its unite pass leaves the lists as they are.
+    if (PASS == kPassUnite) unite_tile<kUniteThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts, c.model != 1);
     else store_tile<kForestThreads>(d, st, tile, threadIdx.x, S.HK);
 }
 
@@ -981,7 +1028,9 @@ hipError_t with_tile_shape(int shape, Args &&...args)
     }
 }
 
-// Launchers of the model-independent kernels (tile_common.hip).
+// Launchers of the model-independent kernels (tile_common.hip): the unite
+// pass alone, or the unite and store passes.
+hipError_t launch_unite(const Chain &c, hipStream_t st, const LaunchHook &hook);
 hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook);
 
 // Per-model chain launchers (ising_tiled.hip, on_tiled.hip).
