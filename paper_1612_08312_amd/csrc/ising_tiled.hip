@@ -121,11 +121,12 @@ template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
 {
     __shared__ IsingTileLds<TX, TY, TZ> S;
-    const int rep = c.tile_rep[blockIdx.x];
+    const int blk = blockIdx.x;
+    const int rep = c.tile_rep[blk];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    ising_tile_pass<TX, TY, TZ>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+    ising_tile_pass<TX, TY, TZ>(d, st, blk - d.tile_base, threadIdx.x, S);
 }
 
 // XOR flip of the int8 spins of `cell` selected by `flipmask` (bit k = site
@@ -314,17 +315,18 @@ template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX *TY *TZ) void k_settle_flip_ising(Chain c)
 {
     __shared__ IsingSettleLds<TX, TY, TZ> S;
-    const int rep = c.tile_rep[blockIdx.x];
+    const int blk = blockIdx.x;
+    const int rep = c.tile_rep[blk];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     if constexpr (TX % 8 == 0) {
         if (d.lgL >= 0) {
-            ising_settle_flip_pass<TX, TY, TZ, true>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+            ising_settle_flip_pass<TX, TY, TZ, true>(d, st, blk - d.tile_base, threadIdx.x, S);
             return;
         }
     }
-    ising_settle_flip_pass<TX, TY, TZ, false>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+    ising_settle_flip_pass<TX, TY, TZ, false>(d, st, blk - d.tile_base, threadIdx.x, S);
 }
 
 // Records and state: energy partials (state before this sweep) into the

@@ -59,11 +59,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
 
-    const int rep = c.tile_rep[blockIdx.x];
+    const int blk = blockIdx.x;
+    const int rep = c.tile_rep[blk];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
+    const int tile = blk - d.tile_base;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
     const float *__restrict__ s = (const float *)d.spins;
     const int64_t N = d.N;
@@ -199,11 +200,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
     __shared__ __align__(16) int LAB[16 * NC];
     __shared__ __align__(16) uint32_t CB[NC];
     __shared__ double red[16];
-    const int rep = c.tile_rep[blockIdx.x];
+    const int blk = blockIdx.x;
+    const int rep = c.tile_rep[blk];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
+    const int tile = blk - d.tile_base;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
     const int tid = threadIdx.x;
     const int L = d.L;

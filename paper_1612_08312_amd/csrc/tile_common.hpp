@@ -1004,11 +1004,12 @@ __global__ __launch_bounds__(PASS == kPassUnite ? kUniteThreads : kForestThreads
         UniteLds u;
         int HK[kTileRoots];
     } S;
-    const int rep = c.tile_rep[blockIdx.x];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int rep = c.tile_rep[blk];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    const int tile = blockIdx.x - d.tile_base;
+    const int tile = blk - d.tile_base;
     // The Ising chain settles its roots in the flip pass and runs no store
     // pass, so its unite pass leaves the lists as they are.
     if (PASS == kPassUnite) unite_tile<kUniteThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts, c.model != 1);
