@@ -42,8 +42,8 @@ def bytes_per_site(shape):
     return {
         "local": 1.0 + 4.0,            # read spins, write tile-local roots
         "unite": 0.0,                  # forest walks over the crossing lists (data dependent)
-        "canon_store": 0.0,            # idem (O(n) chains; the Ising flip settles its own roots)
-        "flip": 4.0 + 1.0 + 1.0,       # read labels, read and write spins (root settling walks and coins not counted)
+        "flip": 4.0 + 1.0 + 1.0,       # read labels, read and write spins (the settle step's walks and stores,
+                                       # data dependent, and the coins drawn in the kernel are not counted)
         "persist": 11.0,               # the whole sweep (every pass), per sweep of each lattice
         "energy": 1.0,                 # read spins
         "finalize": 0.0,
@@ -422,14 +422,15 @@ def graph_throughput(sweeps, stream, dev):
 def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs, counters_valid):
     """Each Ising pass of one L=128 lattice (per-sweep launches, mean over the
     probe): its duration, what bounds it, and the fraction of that bound it
-    reaches.  The tile pass and the flip are bound by VALU issue (wave
-    instructions per launch from the counters / duration, against one wave
-    instruction per CU and cycle); the unite pass by device atomics
+    reaches.  The tile pass is bound by VALU issue (wave instructions per
+    launch from the counters / duration, against one wave instruction per CU
+    and cycle); the settle-and-flip pass by streaming its 6 B/site (labels
+    and spins, against 8 TB/s) and by the latency of its settle walks; the
+    unite pass by device atomics
     (compare-and-swaps per launch / duration, against the measured random
     compare-and-swap rate); the finalize by launch latency (one workgroup
-    per lattice).  The Ising chain has no store pass: each tile settles its
-    own hooked roots at the start of its flip (a store row appears only for
-    chains that run one)."""
+    per lattice).  There is no store pass: each tile settles its own hooked
+    roots at the start of its flip."""
     out = {}
     for k, (n, ms) in kt.items():
         if not n:
@@ -449,19 +450,13 @@ def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs
                        hooks_per_launch=round(hooks_per_launch), achieved_cas_per_s=cas_per_launch / (us * 1e-6),
                        peak_cas_per_s=cas_ceiling, frac=cas_per_launch / (us * 1e-6) / cas_ceiling)
         elif k == "flip":
-            row["bound"] = "VALU issue"
+            row["bound"] = "HBM streaming (labels and spins) and the settle step's walk latency"
             if counters_valid and k in MEASURED_ISSUE:
                 valu, salu, waves = MEASURED_ISSUE[k]
                 row.update(valu_per_wave=round(valu / waves), salu_per_wave=round(salu / waves),
                            achieved_wave_instr_per_s=valu / (us * 1e-6), peak_wave_instr_per_s=VALU_ISSUE_PEAK,
                            frac=valu / (us * 1e-6) / VALU_ISSUE_PEAK)
             row.update(alg_bytes_per_site=6.0, hbm_alg_frac=6.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9))
-        elif k == "canon_store":
-            row["bound"] = "forest walks and scattered 4-byte stores"
-            if counters_valid and k in MEASURED_TRAFFIC:
-                gbs = MEASURED_TRAFFIC[k] / (us * 1e-6) / 1e9
-                row.update(counter_bytes_per_launch=MEASURED_TRAFFIC[k], achieved_GBps=gbs, peak_GBps=copy_gbs,
-                           frac_of_copy=gbs / copy_gbs)
         elif k == "finalize":
             row["bound"] = "launch latency (one workgroup per lattice)"
         if counters_valid and k in MEASURED_TRAFFIC:

@@ -198,30 +198,21 @@ __device__ __forceinline__ void ising_flip_pass(const RepDesc &d, const RepState
 template <int TX, int TY, int TZ>
 struct IsingSettleLds {
     IsingFlipLds<TX, TY, TZ> f;
-    uint16_t HL[4 * TX * TY * TZ];  // local keys of hooked local roots (unbounded count: the rest settle in place)
+    uint16_t HL[kSettleListPerCell * TX * TY * TZ];  // local keys of the tile's hooked local roots
     int wtot[TX * TY * TZ / 64];
 };
 
-// Settle and flip, one workgroup per tile, once every unite is done.  The
-// tile settles its own hooked local roots (entry kTag | p): the walk from p
-// ends at the cluster's tree root, its smallest site, or at an encoding
-// that another settle wrote on the way, and the root's entry becomes the
-// stored encoding (smallest site and coin) in the label array (for later
-// walks and the host's labels) and in the LDS copy of the tile's labels.
-// A local root that is a tree root keeps its own index: its coin is the
-// tile's own coin of that site.  Every local root is settled by its own
-// tile, so no other workgroup writes an entry this one reads from LDS.  The
-// flip then follows ising_flip_pass (ALIGNED = false), or for an aligned
-// tiling (d.lgL >= 0, TX >= 8; see aligned_local_key) stages the labels by
-// local key with 16-byte stores, draws the coin words once per FLIP block
-// and finds each site's coin without division or branch (ALIGNED = true);
-// a hooked site reads its own settled entry.
+// Settle and flip, one workgroup per tile, once every unite is done: the
+// settle step (settle_tile_roots), then the flip as in ising_flip_pass
+// (ALIGNED = false), or for an aligned tiling (d.lgL >= 0, TX >= 8; see
+// aligned_local_key) with the labels staged by local key, the coin words
+// drawn once per FLIP block and each site's coin found without division or
+// branch (ALIGNED = true).
 template <int TX, int TY, int TZ, bool ALIGNED>
 __device__ __forceinline__ void ising_settle_flip_pass(const RepDesc &d, const RepState &st, int tile, int tid,
                                                        IsingSettleLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
-    constexpr int kCapHL = 4 * NC;
     int *LAB = S.f.LAB;
     uint32_t *CB = S.f.CB;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
@@ -230,76 +221,14 @@ __device__ __forceinline__ void ising_settle_flip_pass(const RepDesc &d, const R
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
     const bool valid = ALIGNED || (x < L && y < L && z < L);
     const int cell = cell_index(x, y, z, L);
-    auto pos = [](int key) { return ALIGNED ? key : lds_pos<NC>(key); };
     int lab[16];
-    uint32_t hm = 0;  // bit k: site k of the cell is a hooked local root
-    if (valid) {
-        const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int4 v = L4[q];
-            if (ALIGNED) reinterpret_cast<int4 *>(LAB)[4 * tid + q] = v;
-            lab[4 * q] = v.x;
-            lab[4 * q + 1] = v.y;
-            lab[4 * q + 2] = v.z;
-            lab[4 * q + 3] = v.w;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (!ALIGNED) LAB[k * NC + tid] = lab[k];
-            const bool hooked = ((uint32_t)lab[k] >> 30) == 1u;  // kTag | p
-            hm |= (uint32_t)hooked << k;
-            lab[k] = hooked ? 16 * cell + k : lab[k];  // the flip reads the settled entry of the site itself
-        }
-    }
+    const uint32_t hm = valid ? stage_cell_labels<NC, ALIGNED>(d.label, cell, tid, lab, LAB) : 0u;
     if constexpr (ALIGNED) {
         if (tid < NC / 8) reinterpret_cast<uint4 *>(CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
     } else {
         CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
     }
-    // List places of the thread's hooked roots: after those of the lanes
-    // below it (five ballots of its 0..16 count) and of the lower waves.
-    const uint32_t cnt = (uint32_t)__popc(hm);
-    uint32_t below = 0, wt = 0;
-#pragma unroll
-    for (int bit = 0; bit < 5; ++bit) {
-        const uint64_t b = __ballot((cnt >> bit) & 1u);
-        below += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u)) << bit;
-        wt += (uint32_t)__popcll(b) << bit;
-    }
-    const int wave = tid >> 6;
-    if ((tid & 63) == 0) S.wtot[wave] = (int)wt;
-    __syncthreads();
-    int at = (int)below, nh = 0;
-    for (int w = 0; w < NC / 64; ++w) {
-        const int t = S.wtot[w];
-        at += w < wave ? t : 0;
-        nh += t;
-    }
-    if (hm) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (!((hm >> k) & 1u)) continue;
-            const int key = 16 * tid + k;
-            if (at < kCapHL) {
-                S.HL[at] = (uint16_t)key;
-            } else {  // beyond the list: settled by the thread that found it
-                const int e = canon_encoding(d.label, LAB[pos(key)] & kIdxMask, st.t, d.key);
-                lab_store(d.label, 16 * cell + k, e);
-                LAB[pos(key)] = e;
-            }
-            ++at;
-        }
-    }
-    __syncthreads();
-    const int nl = min(nh, kCapHL);
-    for (int j = tid; j < nl; j += NC) {
-        const int key = S.HL[j];
-        const int e = canon_encoding(d.label, LAB[pos(key)] & kIdxMask, st.t, d.key);
-        lab_store(d.label, ti.global_site(key), e);
-        LAB[pos(key)] = e;
-    }
-    __syncthreads();
+    settle_tile_roots<TX, TY, TZ, ALIGNED>(d, st, ti, tid, cell, hm, LAB, S.HL, S.wtot);
     int mag = 0;
     if (valid) {
         uint32_t flipmask;

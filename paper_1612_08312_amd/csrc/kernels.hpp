@@ -98,11 +98,10 @@ enum KernelId : int {
     kKInit = 0,
     kKLocal,     // tile pass
     kKUnite,     // forest unite pass
-    kKFlip,
+    kKFlip,      // settle and flip
     kKEnergy,    // energy tail
     kKFinalize,
     kKAxis,      // O(n) axis
-    kKCompress,  // forest store pass ("canon_store")
     kKPersist,   // persistent fused sweep (all sweeps of a call)
     kKResident,  // LDS-resident small lattices (all sweeps of a call)
     kNumKernels

@@ -190,58 +190,43 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
     if (tid == 0) d.dpart[tile] = b;
 }
 
-// One workgroup per tile: cluster coins from an LDS copy of the tile's
-// labels and the tile's own coins (as in the Ising flip), reflections, FP64
-// magnetisation.
-template <int NV, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
+// LDS of the O(n) settle-and-flip pass.
+template <int TX, int TY, int TZ>
+struct OnFlipLds {
+    alignas(16) int LAB[16 * TX * TY * TZ];  // labels of the tile's sites
+    alignas(16) uint32_t CB[TX * TY * TZ];   // coins of the tile's sites
+    uint16_t HL[kSettleListPerCell * TX * TY * TZ];  // local keys of the tile's hooked local roots
+    int wtot[TX * TY * TZ / 64];
+    double red[16];
+};
+
+// One workgroup per tile, once every unite is done: the settle step
+// (settle_tile_roots), cluster coins from the LDS copy of the tile's labels
+// and the tile's own coins (as in the Ising flip; ALIGNED as there),
+// reflections, FP64 magnetisation.
+template <int NV, int TX, int TY, int TZ, bool ALIGNED>
+__device__ __forceinline__ void on_settle_flip_pass(const RepDesc &d, const RepState &st, int tile, int tid,
+                                                    OnFlipLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
-    __shared__ __align__(16) int LAB[16 * NC];
-    __shared__ __align__(16) uint32_t CB[NC];
-    __shared__ double red[16];
-    const int blk = blockIdx.x;
-    const int rep = c.tile_rep[blk];
-    const RepState st = *c.state[rep];
-    if (st.remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    const int tile = blk - d.tile_base;
+    int *LAB = S.LAB;
+    uint32_t *CB = S.CB;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
-    const int tid = threadIdx.x;
     const int L = d.L;
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int x = ti.bx * TX + lx, y = ti.by * TY + ly, z = ti.bz * TZ + lz;
-    const bool valid = x < L && y < L && z < L;
+    const bool valid = ALIGNED || (x < L && y < L && z < L);
     const int cell = cell_index(x, y, z, L);
     const int64_t N = d.N;
     float *s = (float *)d.spins;
-    // An aligned tiling (TX >= 8) stages the labels by local key and draws
-    // the coin words once per FLIP block (as the aligned Ising flip does).
-    bool aligned = false;
-    if constexpr (TX % 8 == 0) aligned = d.lgL >= 0;  // uniform
     int lab[16];
-    if (valid) {
-        const int4 *L4 = reinterpret_cast<const int4 *>(d.label + 16 * cell);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int4 v = L4[q];
-            lab[4 * q] = v.x;
-            lab[4 * q + 1] = v.y;
-            lab[4 * q + 2] = v.z;
-            lab[4 * q + 3] = v.w;
-            if (aligned) reinterpret_cast<int4 *>(LAB)[4 * tid + q] = v;
-        }
-        if (!aligned) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) LAB[k * NC + tid] = lab[k];
-        }
+    const uint32_t hm = valid ? stage_cell_labels<NC, ALIGNED>(d.label, cell, tid, lab, LAB) : 0u;
+    if constexpr (ALIGNED) {
+        if (tid < NC / 8) reinterpret_cast<uint4 *>(CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
+    } else {
+        CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
     }
-    if constexpr (TX % 8 == 0) {
-        if (aligned && tid < NC / 8)
-            reinterpret_cast<uint4 *>(CB)[tid] = aligned_coin_words<TX, TY, TZ>(ti, tid, st.t, d.key);
-    }
-    if (!aligned) CB[tid] = valid ? cell_coins(cell, st.t, d.key) : 0u;
-    __syncthreads();
+    settle_tile_roots<TX, TY, TZ, ALIGNED>(d, st, ti, tid, cell, hm, LAB, S.HL, S.wtot);
     double M[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) M[k] = 0.0;
@@ -250,12 +235,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
         uint32_t flipmask;
-        if constexpr (TX % 8 == 0) {
-            flipmask = aligned ? cell_flip_mask_aligned<TX, TY, TZ>(lab, LAB, CB, d.lgL)
-                               : cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
-        } else {
-            flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
-        }
+        if constexpr (ALIGNED) flipmask = cell_flip_mask_aligned<TX, TY, TZ>(lab, LAB, CB, d.lgL);
+        else flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
         float v[NV][16];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -295,9 +276,26 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_flip_on(Chain c)
     }
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const double b = block_sum<double>(M[k], red);
+        const double b = block_sum<double>(M[k], S.red);
         if (tid == 0) d.dpart[d.mpart_off * (1 + k) + tile] = b;
     }
+}
+
+template <int NV, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_settle_flip_on(Chain c)
+{
+    __shared__ OnFlipLds<TX, TY, TZ> S;
+    const int rep = c.tile_rep[blockIdx.x];
+    const RepState st = *c.state[rep];
+    if (st.remaining <= 0) return;
+    const RepDesc &d = c.desc[rep];
+    if constexpr (TX % 8 == 0) {
+        if (d.lgL >= 0) {
+            on_settle_flip_pass<NV, TX, TY, TZ, true>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+            return;
+        }
+    }
+    on_settle_flip_pass<NV, TX, TY, TZ, false>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
 }
 
 // Records and state (see k_finalize_ising).
@@ -408,7 +406,7 @@ struct OnFlip {
     template <int TX, int TY, int TZ>
     static hipError_t run(const Chain &c, hipStream_t st, const LaunchHook &hook)
     {
-        PYRO_LAUNCH(kKFlip, (k_flip_on<NV, TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
+        PYRO_LAUNCH(kKFlip, (k_settle_flip_on<NV, TX, TY, TZ>), c.ntile_blocks, TX * TY * TZ, c);
         return hipSuccess;
     }
 };
@@ -418,7 +416,7 @@ static hipError_t sweep_on(const Chain &c, hipStream_t st, const LaunchHook &hoo
 {
     PYRO_LAUNCH(kKAxis, k_axis, c.nreps, 64, c);
     hipError_t e = with_tile_shape<OnLocal<NV>>(c.shape, c, st, hook);
-    if (e == hipSuccess) e = launch_merge(c, st, hook);
+    if (e == hipSuccess) e = launch_unite(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<OnFlip<NV>>(c.shape, c, st, hook);
     if (e != hipSuccess) return e;
     PYRO_LAUNCH(kKFinalize, k_finalize_on<NV>, c.nreps, kFinalizeThreads, c);

@@ -27,16 +27,8 @@ __global__ __launch_bounds__(kBlock) void k_canonical_labels(const int32_t *__re
 
 hipError_t launch_unite(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
-    if (c.counts) PYRO_LAUNCH(kKUnite, (k_forest<kPassUnite, true>), c.ntile_blocks, kUniteThreads, c);
-    else PYRO_LAUNCH(kKUnite, k_forest<kPassUnite>, c.ntile_blocks, kUniteThreads, c);
-    return hipSuccess;
-}
-
-hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook)
-{
-    const hipError_t e = launch_unite(c, st, hook);
-    if (e != hipSuccess) return e;
-    PYRO_LAUNCH(kKCompress, k_forest<kPassStore>, c.ntile_blocks, kForestThreads, c);
+    if (c.counts) PYRO_LAUNCH(kKUnite, k_forest<true>, c.ntile_blocks, kUniteThreads, c);
+    else PYRO_LAUNCH(kKUnite, k_forest<false>, c.ntile_blocks, kUniteThreads, c);
     return hipSuccess;
 }
 

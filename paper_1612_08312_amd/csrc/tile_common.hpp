@@ -449,6 +449,103 @@ __device__ __forceinline__ uint4 aligned_coin_words(const TileIdx<TX, TY, TZ> &t
     return philox4x32_10((uint32_t)gcell >> 3, t, kStreamFlip, 0u, key);
 }
 
+// ------------------------------------------------------- settle step ---
+// The flip kernels settle their tile's own hooked local roots (entries
+// kTag | p) once every unite is done: the walk from p ends at the
+// cluster's tree root, its smallest site, or at an encoding that another
+// settle wrote on the way, and the root's entry becomes the stored encoding
+// (smallest site and coin) in the label array, for later walks and the
+// host's labels, and in the LDS copy of the tile's labels.  A local root
+// that is a tree root keeps its own index: its cluster's coin is the
+// tile's own coin of that site (the same bit of the same FLIP word).  Only
+// a root's own tile settles it, so no other workgroup changes an entry a
+// tile has staged.
+constexpr int kSettleListPerCell = 4;  // list room per cell; roots beyond it settle in place
+
+// Loads the 16 labels of a flip kernel's cell into lab and copies them into
+// LAB (by local key on an aligned tiling, else at lds_pos).  Returns the
+// mask of the sites that are hooked local roots; their lab value becomes
+// the site's own index, so that the flip reads the site's settled entry.
+template <int NC, bool ALIGNED>
+__device__ __forceinline__ uint32_t stage_cell_labels(const int32_t *label, int cell, int tid, int (&lab)[16], int *LAB)
+{
+    const int4 *L4 = reinterpret_cast<const int4 *>(label + 16 * cell);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int4 v = L4[q];
+        if (ALIGNED) reinterpret_cast<int4 *>(LAB)[4 * tid + q] = v;
+        lab[4 * q] = v.x;
+        lab[4 * q + 1] = v.y;
+        lab[4 * q + 2] = v.z;
+        lab[4 * q + 3] = v.w;
+    }
+    uint32_t hm = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (!ALIGNED) LAB[k * NC + tid] = lab[k];
+        const bool hooked = ((uint32_t)lab[k] >> 30) == 1u;  // kTag | p
+        hm |= (uint32_t)hooked << k;
+        lab[k] = hooked ? 16 * cell + k : lab[k];
+    }
+    return hm;
+}
+
+// The settle step of a flip kernel (all NC threads of the tile, after
+// stage_cell_labels; hm is the thread's mask, 0 for a thread without a
+// cell).  The hooked roots are listed in HL (kSettleListPerCell NC
+// entries; the list places follow the threads' counts, by five ballots
+// and the wave totals in wtot, NC / 64 ints) and settled by all threads.
+template <int TX, int TY, int TZ, bool ALIGNED>
+__device__ __forceinline__ void settle_tile_roots(const RepDesc &d, const RepState &st, const TileIdx<TX, TY, TZ> &ti,
+                                                  int tid, int cell, uint32_t hm, int *LAB, uint16_t *HL, int *wtot)
+{
+    constexpr int NC = TX * TY * TZ;
+    constexpr int kCapHL = kSettleListPerCell * NC;
+    static_assert(16 * NC <= 65536, "local keys fit 16 bits");
+    auto pos = [](int key) { return ALIGNED ? key : lds_pos<NC>(key); };
+    const uint32_t cnt = (uint32_t)__popc(hm);
+    uint32_t below = 0, wt = 0;
+#pragma unroll
+    for (int bit = 0; bit < 5; ++bit) {
+        const uint64_t b = __ballot((cnt >> bit) & 1u);
+        below += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u)) << bit;
+        wt += (uint32_t)__popcll(b) << bit;
+    }
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) wtot[wave] = (int)wt;
+    __syncthreads();
+    int at = (int)below, nh = 0;
+    for (int w = 0; w < NC / 64; ++w) {
+        const int t = wtot[w];
+        at += w < wave ? t : 0;
+        nh += t;
+    }
+    if (hm) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (!((hm >> k) & 1u)) continue;
+            const int key = 16 * tid + k;
+            if (at < kCapHL) {
+                HL[at] = (uint16_t)key;
+            } else {  // beyond the list: settled by the thread that found it
+                const int e = canon_encoding(d.label, LAB[pos(key)] & kIdxMask, st.t, d.key);
+                lab_store(d.label, 16 * cell + k, e);
+                LAB[pos(key)] = e;
+            }
+            ++at;
+        }
+    }
+    __syncthreads();
+    const int nl = min(nh, kCapHL);
+    for (int j = tid; j < nl; j += NC) {
+        const int key = HL[j];
+        const int e = canon_encoding(d.label, LAB[pos(key)] & kIdxMask, st.t, d.key);
+        lab_store(d.label, ti.global_site(key), e);
+        LAB[pos(key)] = e;
+    }
+    __syncthreads();
+}
+
 // Site `site` of the neighbour cell `code` (lattice.hpp codes) of the cell
 // at (x, y, z); xm, ym, zm are the wrapped lower coordinates.  Bit 0/1/2 of
 // the 3-bit field of a code says whether the neighbour is one cell lower in
@@ -735,14 +832,14 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 }
 
 // ------------------------------------------------------- forest passes ---
-// Passes over the tiles' crossing lists, one workgroup of kBlock threads per
-// tile (two launches, the second seeing the first complete):
-//   kPassUnite  unite the local roots of the two names of every pair;
-//   kPassStore  store the encoded root of its tree (the cluster's smallest
-//               site and its flip coin) in every local root of the list
-//               (walks stop at the first stored encoding, so they shorten as
-//               the pass proceeds).
-enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
+// Work on the tiles' crossing lists, one workgroup per tile:
+//   unite  unite the local roots of the two names of every pair (the unite
+//          pass of every chain, and a phase of the persistent kernel);
+//   store  store the encoded root of its tree (the cluster's smallest site
+//          and its flip coin) in every local root of the list (walks stop
+//          at the first stored encoding, so they shorten as the pass
+//          proceeds); only the persistent kernel runs it, the chains
+//          settle their roots in the flip pass instead.
 
 // Unite pass of one tile (kBlock threads).  The pairs of a tile mostly share
 // a few local roots, so hooking them one by one makes the tile's threads
@@ -764,7 +861,6 @@ enum GlobalPass : int { kPassUnite = 0, kPassStore = 1 };
 // hooked under, and its entry (itself) is already its canonical form.
 constexpr int kTileRoots = 1024;  // LDS root table of the unite pass
 
-constexpr int kForestThreads = 512;  // threads per tile in the store pass
 constexpr int kUniteThreads = 256;   // threads per tile in the unite pass (its CAS chains are latency bound;
                                      // smaller workgroups let more tiles run at once)
 
@@ -995,25 +1091,19 @@ __device__ __forceinline__ void unite_tile(const RepDesc &d, int tile, int tid, 
     unite_tile_pairs<NT, COUNT>(d.label, head, head[0], d.list_stride, tid, S, counts, keep_roots);
 }
 
-// PASS: kPassUnite or kPassStore; COUNT: the unite pass counts its
-// compare-and-swaps into c.counts (measurement runs).
-template <int PASS, bool COUNT = false>
-__global__ __launch_bounds__(PASS == kPassUnite ? kUniteThreads : kForestThreads) void k_forest(Chain c)
+// The unite pass of a chain.  COUNT: it counts its compare-and-swaps into
+// c.counts (measurement runs).  The chains settle their roots in the flip
+// pass and run no store pass, so the lists are left as they are.
+template <bool COUNT = false>
+__global__ __launch_bounds__(kUniteThreads) void k_forest(Chain c)
 {
-    __shared__ union {
-        UniteLds u;
-        int HK[kTileRoots];
-    } S;
+    __shared__ UniteLds S;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int rep = c.tile_rep[blk];
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    const int tile = blk - d.tile_base;
-    // The Ising chain settles its roots in the flip pass and runs no store
-    // pass, so its unite pass leaves the lists as they are.
-    if (PASS == kPassUnite) unite_tile<kUniteThreads, COUNT>(d, tile, threadIdx.x, S.u, c.counts, c.model != 1);
-    else store_tile<kForestThreads>(d, st, tile, threadIdx.x, S.HK);
+    unite_tile<kUniteThreads, COUNT>(d, blk - d.tile_base, threadIdx.x, S, c.counts, false);
 }
 
 // Shape dispatch: calls F::template run<TX, TY, TZ>(args...).
@@ -1029,10 +1119,8 @@ hipError_t with_tile_shape(int shape, Args &&...args)
     }
 }
 
-// Launchers of the model-independent kernels (tile_common.hip): the unite
-// pass alone, or the unite and store passes.
+// Launcher of the model-independent unite pass (tile_common.hip).
 hipError_t launch_unite(const Chain &c, hipStream_t st, const LaunchHook &hook);
-hipError_t launch_merge(const Chain &c, hipStream_t st, const LaunchHook &hook);
 
 // Per-model chain launchers (ising_tiled.hip, on_tiled.hip).
 hipError_t launch_ising_sweep(const Chain &c, hipStream_t st, const LaunchHook &hook);
