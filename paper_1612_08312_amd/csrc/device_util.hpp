@@ -20,7 +20,9 @@ __device__ __forceinline__ int cell_index(int x, int y, int z, int L) { return m
 // Deterministic sum over a block (blockDim.x multiple of 64, at most 1024):
 // fixed shuffle tree inside each wave, then the wave sums in wave order.
 // Result valid in thread 0.
-template <typename T>
+// kReuse = false drops the closing barrier, which only protects lds from
+// the block's next use of it: for a kernel's last use of its LDS.
+template <typename T, bool kReuse = true>
 __device__ __forceinline__ T block_sum(T v, T *lds /* >= 16 entries */)
 {
 #pragma unroll
@@ -33,7 +35,7 @@ __device__ __forceinline__ T block_sum(T v, T *lds /* >= 16 entries */)
         const int nw = blockDim.x / kWave;
         for (int w = 0; w < nw; ++w) s += lds[w];
     }
-    __syncthreads();
+    if (kReuse) __syncthreads();
     return s;
 }
 

@@ -53,7 +53,9 @@ struct IsingFlipLds {
     int64_t red[16];
 };
 
-template <int TX, int TY, int TZ>
+// kLast: the pass is the kernel's last use of its LDS (k_local_ising, not
+// the persistent kernel).
+template <int TX, int TY, int TZ, bool kLast = false>
 __device__ __forceinline__ void ising_tile_pass(const RepDesc &d, const RepState &st, int tile, int tid,
                                                 IsingTileLds<TX, TY, TZ> &S)
 {
@@ -113,7 +115,7 @@ __device__ __forceinline__ void ising_tile_pass(const RepDesc &d, const RepState
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
     tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4);
-    const int64_t bsum = block_sum<int64_t>(valid ? (int64_t)(2 * aligned_count - nbonds) : 0, red);
+    const int64_t bsum = block_sum<int64_t, !kLast>(valid ? (int64_t)(2 * aligned_count - nbonds) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }
 
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_ising(Chain c)
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
-    ising_tile_pass<TX, TY, TZ>(d, st, blk - d.tile_base, threadIdx.x, S);
+    ising_tile_pass<TX, TY, TZ, true>(d, st, blk - d.tile_base, threadIdx.x, S);
 }
 
 // XOR flip of the int8 spins of `cell` selected by `flipmask` (bit k = site
@@ -236,7 +238,7 @@ __device__ __forceinline__ void ising_settle_flip_pass(const RepDesc &d, const R
         else flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
         mag = flip_cell(d.spins, cell, flipmask);
     }
-    const int64_t msum = block_sum<int64_t>((int64_t)mag, S.f.red);
+    const int64_t msum = block_sum<int64_t, false>((int64_t)mag, S.f.red);
     if (tid == 0) d.ipart[d.mpart_off + tile] = msum;
 }
 

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
         }
     }
     tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, DA, K4);
-    const double b = block_sum<double>(esum, red);
+    const double b = block_sum<double, false>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }
 

@@ -646,7 +646,8 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 {
     constexpr int NC = TX * TY * TZ;
     static_assert(NC % 64 == 0, "tiles are whole waves");
-    constexpr int kCap = kUnionsPerCell * NC;
+    constexpr int kCap = kUnionsPerCell * NC - NC / 64;  // union list; its wave totals follow it in U
+    uint32_t *WT = U + kCap;
     // local key of vertex mu of down tetrahedron f (-1 when outside the tile)
     auto vkey = [&](int f, int mu) {
         const SiteRef R = down_vertex(f, mu);
@@ -661,7 +662,8 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) node(P, base + 4 * mu) = base + 4 * ((code >> (2 * mu)) & 3);
     }
-    __syncthreads();
+    // No barrier here: the down tetrahedra below read only registers and K4,
+    // and the forest is first read after the barrier of the list placement.
     // Down tetrahedra, inside the tile: spanning edges, packed as two 16-bit
     // forest slots (17 NC < 2^16).
     uint32_t un[12];
@@ -692,7 +694,9 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         }
     }
     // The thread's unions go after those of the lanes below it (four ballots
-    // of its 0..12 count) and of the lower waves (totals in DA, free here).
+    // of its 0..12 count) and of the lower waves (totals in WT, past the
+    // list's room in U; DA may still be read by a slower thread's bond
+    // activation, which is why it does not hold them).
     uint32_t below = 0, wtot = 0;
 #pragma unroll
     for (int bit = 0; bit < 4; ++bit) {
@@ -701,12 +705,12 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
         wtot += (uint32_t)__popcll(b) << bit;
     }
     const int wave = tid >> 6;
-    if ((tid & 63) == 0) DA[wave] = wtot;
+    if ((tid & 63) == 0) WT[wave] = wtot;
     __syncthreads();
     int ntotal = 0;
     unsigned at = below;
     for (int w = 0; w < NC / 64; ++w) {
-        const int t = (int)DA[w];
+        const int t = (int)WT[w];
         at += w < wave ? t : 0;
         ntotal += t;
     }
@@ -826,7 +830,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
             at += e[k];
         }
         placed += total;
-        __syncthreads();
+        if (jb + NC < kItems) __syncthreads();  // U[wave] is rewritten by the next round
     }
     if (tid == 0) d.pairs[(int64_t)tile * d.list_stride] = placed;
 }
