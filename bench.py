@@ -56,9 +56,18 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = None
-MEASURED_TRAFFIC = {}  # kernel -> HBM bytes per launch
-MEASURED_ISSUE = {}    # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
+COUNTER_FINGERPRINT = "431b96b5765ce7fe"
+MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
+    "local": 216843424,
+    "unite": 194597418,
+    "flip": 269849152,
+    "finalize": 73139,
+}
+MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
+    "local": (60720284, 24649036, 32768),
+    "unite": (11533234, 12804587, 16384),
+    "flip": (25087033, 10713601, 32768),
+}
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a
 # 16-lane SIMD for 4 cycles, so each of the 256 CUs (4 SIMDs) completes at
@@ -424,8 +433,10 @@ def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs
     probe): its duration, what bounds it, and the fraction of that bound it
     reaches.  The tile pass is bound by VALU issue (wave instructions per
     launch from the counters / duration, against one wave instruction per CU
-    and cycle); the settle-and-flip pass by streaming its 6 B/site (labels
-    and spins, against 8 TB/s) and by the latency of its settle walks; the
+    and cycle); the settle-and-flip pass by HBM streaming (counter bytes /
+    duration, against 8 TB/s and the measured copy bandwidth: its 6 B/site
+    of labels and spins plus the settle step's walks) and by the latency of
+    its settle walks; the
     unite pass by device atomics
     (compare-and-swaps per launch / duration, against the measured random
     compare-and-swap rate); the finalize by launch latency (one workgroup
@@ -451,12 +462,15 @@ def kernel_bounds(kt, N, cas_per_launch, hooks_per_launch, cas_ceiling, copy_gbs
                        peak_cas_per_s=cas_ceiling, frac=cas_per_launch / (us * 1e-6) / cas_ceiling)
         elif k == "flip":
             row["bound"] = "HBM streaming (labels and spins) and the settle step's walk latency"
+            row.update(alg_bytes_per_site=6.0, hbm_alg_frac=6.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9))
+            if counters_valid and k in MEASURED_TRAFFIC:
+                gbs = MEASURED_TRAFFIC[k] / (us * 1e-6) / 1e9
+                row.update(achieved_GBps=gbs, peak_GBps=HBM_PEAK_GBS, frac=gbs / HBM_PEAK_GBS,
+                           frac_of_copy=gbs / copy_gbs)
             if counters_valid and k in MEASURED_ISSUE:
                 valu, salu, waves = MEASURED_ISSUE[k]
                 row.update(valu_per_wave=round(valu / waves), salu_per_wave=round(salu / waves),
-                           achieved_wave_instr_per_s=valu / (us * 1e-6), peak_wave_instr_per_s=VALU_ISSUE_PEAK,
-                           frac=valu / (us * 1e-6) / VALU_ISSUE_PEAK)
-            row.update(alg_bytes_per_site=6.0, hbm_alg_frac=6.0 * N / (us * 1e-6) / (HBM_PEAK_GBS * 1e9))
+                           valu_issue_frac=valu / (us * 1e-6) / VALU_ISSUE_PEAK)
         elif k == "finalize":
             row["bound"] = "launch latency (one workgroup per lattice)"
         if counters_valid and k in MEASURED_TRAFFIC:
