@@ -149,8 +149,8 @@ def test_large_tiles_with_long_crossing_lists(T):
     """16x8x8 tiles on a ragged L = 100 lattice: 609 crossing tetrahedra per
     tile, each emitting up to 3 pairs; in the ordered phase (T = 3) most emit
     2 or 3, so a tile's list exceeds the unite pass's 1024 LDS pair slots and
-    the direct unions run (and, with many distinct roots, the pair-list
-    fallback of the store pass).  Results must equal the 8x8x8 tiling."""
+    the direct unions run (and, with many distinct roots, those beyond the
+    LDS root table).  Results must equal the 8x8x8 tiling."""
     out = []
     for shape in (3, 4):
         x = lat(L=100, model=1, T=T, seed=31, start=1)
