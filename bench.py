@@ -56,17 +56,17 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "431b96b5765ce7fe"
+COUNTER_FINGERPRINT = "61512be10e4b3788"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
-    "local": 216843424,
-    "unite": 194597418,
-    "flip": 269849152,
+    "local": 216841833,
+    "unite": 194593080,
+    "flip": 269822389,
     "finalize": 73139,
 }
 MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
-    "local": (60720284, 24649036, 32768),
-    "unite": (11533234, 12804587, 16384),
-    "flip": (25087033, 10713601, 32768),
+    "local": (60720311, 24649168, 32768),
+    "unite": (11533260, 12804393, 16384),
+    "flip": (25087263, 10713834, 32768),
 }
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a

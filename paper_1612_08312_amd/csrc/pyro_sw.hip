@@ -1424,9 +1424,21 @@ static int group_run(pyro_sw_group *g, int64_t reps)
     if (g->subs.size() == 1) {
         if (int rc = run_slice(g->subs[0], g->stream)) return rc;
     } else {
+        // The slices' sweeps are enqueued round robin in blocks of
+        // kEnqueueBlock: enqueued slice by slice, a long call filled the
+        // first slice's queue and blocked the host there while the other
+        // slices had no work yet (one call of 10^4 sweeps of five L = 128
+        // lattices ran at 1.55 ms per step instead of 1.42).
+        constexpr int64_t kEnqueueBlock = 64;
         for (auto &sg : g->subs) {
             HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(sg.stream, g->fork, 0));
-            if (int rc = run_slice(sg, sg.stream)) return rc;
+            if (sg.pexec) HIP_OR_FAIL(&g->broken, hipGraphLaunch(sg.pexec, sg.stream));
+        }
+        for (int64_t k0 = 0; k0 < reps; k0 += kEnqueueBlock)
+            for (auto &sg : g->subs)
+                for (int64_t k = k0; k < std::min(reps, k0 + kEnqueueBlock); ++k)
+                    if (sg.exec) HIP_OR_FAIL(&g->broken, hipGraphLaunch(sg.exec, sg.stream));
+        for (auto &sg : g->subs) {
             HIP_OR_FAIL(&g->broken, hipEventRecord(sg.join, sg.stream));
             HIP_OR_FAIL(&g->broken, hipStreamWaitEvent(g->stream, sg.join, 0));
         }
