@@ -56,7 +56,7 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "61512be10e4b3788"
+COUNTER_FINGERPRINT = "19f5e09f694700cc"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
     "local": 216841833,
     "unite": 194593080,
@@ -75,8 +75,34 @@ MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions,
 VALU_ISSUE_PEAK = 256 * 2.4e9
 
 
+def _code_tokens(text):
+    """Source text without comments, whitespace runs collapsed (string and
+    character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_fingerprint():
-    """SHA-256 over the HIP sources of the library (names and contents)."""
+    """SHA-256 over the HIP sources of the library (names and code, comments
+    and whitespace left out, so that a comment edit keeps the counters)."""
     import hashlib
 
     h = hashlib.sha256()
@@ -84,8 +110,8 @@ def kernel_fingerprint():
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp")):
             h.update(name.encode())
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
+                h.update(_code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -36,7 +36,7 @@
 
 namespace pyro {
 
-// LDS of the tile pass and of the flip pass of one tile.
+// LDS of the tile pass and of the flip of one tile.
 template <int TX, int TY, int TZ>
 struct IsingTileLds {
     uint32_t P[kForestSlots<TX * TY * TZ>];     // tile forest

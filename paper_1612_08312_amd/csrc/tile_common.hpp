@@ -218,9 +218,10 @@ struct TileIdx {
 // encodings of a local root r:
 //   r                   r is a root of the merged forest
 //   kTag | p            r was hooked under p
-//   kCanonBase + c (| kCoinBit)  written by the store pass: c is the
-//                       smallest site index of r's cluster, and kCoinBit is
-//                       set when that cluster flips in this sweep
+//   kCanonBase + c (| kCoinBit)  written by the settle step of the flip
+//                       kernels (or the persistent kernel's store phase): c is
+//                       the smallest site index of r's cluster, and kCoinBit
+//                       is set when that cluster flips in this sweep
 // Site indices are below 2^30 (L <= 406), so the three forms are distinct and
 // the local root of any site is decodable at any time, even while other
 // threads hook roots or store canonical labels: an entry that is negative,
@@ -228,9 +229,10 @@ struct TileIdx {
 //
 // A root is always hooked under the smaller of the two roots, so every tree
 // root is the smallest local root of its tree, i.e. the smallest site of
-// its cluster, and the store pass only has to copy it into every local root
-// of the cluster.  The unite pass hooks each tile's group of roots under
-// its smallest member in one step, which keeps the trees shallow.
+// its cluster, and settling a hooked local root only has to copy it (with
+// its coin) into the root's entry.  The unite pass hooks each tile's group
+// of roots under its smallest member in one step, which keeps the trees
+// shallow.
 constexpr int kTag = 1 << 30;
 constexpr int kIdxMask = kTag - 1;
 constexpr int kCanonBase = INT32_MIN;  // canonical index c is stored as kCanonBase + c
@@ -257,7 +259,7 @@ __device__ __forceinline__ uint32_t cell_coins(int cell, uint32_t t, PhiloxKey k
 // go past the per-XCD L2 on every step of every walk).  A stale value is an
 // older value of the same entry, and every value an entry ever holds is an
 // ancestor of the node in the final forest (hooks link roots, shortcuts
-// store ancestors, the store pass writes only encodings that end a walk),
+// store ancestors, the settle step writes only encodings that end a walk),
 // so a stale walk is only longer, never wrong; the updates that decide the
 // forest (hook CAS) are device-wide atomics and return the current value.  Launch boundaries make all writes visible.
 __device__ __forceinline__ int lab_load(const int32_t *lab, int x)
@@ -317,8 +319,8 @@ __device__ __forceinline__ void forest_unite(int32_t *lab, int a, int b, unsigne
     }
 }
 
-// Tree root of local root x after the unite pass, or the first encoding the
-// store pass has already written on the way (a negative value).  The tree
+// Tree root of local root x after the unite pass, or the first encoding a
+// settle step has already written on the way (a negative value).  The tree
 // root's index is the cluster's smallest site.
 __device__ __forceinline__ int root_or_encoding(const int32_t *lab, int x)
 {
@@ -340,8 +342,8 @@ __device__ __forceinline__ int canon_encoding(const int32_t *lab, int x, uint32_
 }
 
 // Canonical label (smallest site index of the cluster) of any site once the
-// store pass is done: site -> local root -> itself or its encoding (a walk
-// from a still-hooked local root is kept as a safeguard).
+// sweep is done: site -> local root -> itself (a tree root) or its settled
+// encoding (a walk from a still-hooked local root is kept as a safeguard).
 __device__ __forceinline__ int canonical_label(const int32_t *label, int64_t i)
 {
     const int v = label[i];
@@ -853,12 +855,12 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 // then target distinct roots.  Pairs beyond the LDS tables are united
 // directly.
 //
-// When a store pass follows (keep_roots), the tile's list is then replaced
-// by its distinct local roots, which is all the store pass needs: it skips
-// resolving names again.  With room for it
+// When a store phase follows (keep_roots: the persistent kernel), the
+// tile's list is then replaced by its distinct local roots, which is all
+// the store phase needs: it skips resolving names again.  With room for it
 // (list_stride >= 2 + 2 H), head[1] = -m and the m roots from head[2] on are
 // followed, from head[2 + H] on, by the list position of each root's group
-// representative, so the store pass walks once per group.  Otherwise
+// representative, so the store phase walks once per group.  Otherwise
 // head[1] = m and only the roots are written.  head[1] = 0 keeps the pairs
 // (some root did not fit in the table).  A local root that occurs only in
 // pairs whose two names resolve to it is left out: it is never hooked nor
@@ -869,7 +871,7 @@ constexpr int kUniteThreads = 256;   // threads per tile in the unite pass (its 
                                      // smaller workgroups let more tiles run at once)
 
 // LDS words that other threads of the workgroup change concurrently (root
-// tables and parent slots of the unite and store passes) are read and
+// tables and parent slots of the unite pass and the store phase) are read and
 // written with relaxed workgroup-scope atomics, so that no load is hoisted
 // out of a retry loop or served from a register copy.
 __device__ __forceinline__ int lds_ld(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
@@ -1026,7 +1028,8 @@ __device__ __forceinline__ void unite_tile_pairs(int32_t *lab, int *head, int n,
     if (tid == 0 && keep_roots) head[1] = S.missed ? 0 : (with_reps ? -S.nroots : S.nroots);
 }
 
-// Store pass of one tile (NT threads; HK: kTileRoots ints of LDS).
+// Store phase of one tile in the persistent kernel (NT threads; HK:
+// kTileRoots ints of LDS).
 template <int NT>
 __device__ __forceinline__ void store_tile(const RepDesc &d, const RepState &st, int tile, int tid, int *HK)
 {
