@@ -206,15 +206,15 @@ struct IsingSettleLds {
 
 // Settle and flip, one workgroup per tile, once every unite is done: the
 // settle step (settle_tile_roots), then the flip as in ising_flip_pass
-// (ALIGNED = false), or for an aligned tiling (d.lgL >= 0, TX >= 8; see
-// aligned_local_key) with the labels staged by local key, the coin words
-// drawn once per FLIP block and each site's coin found without division or
-// branch (ALIGNED = true).
-template <int TX, int TY, int TZ, bool ALIGNED>
+// (MODE = kFlipGeneral), or, when the tile edges divide L and TX >= 8
+// (FlipMode), with the labels staged by local key, the coin words drawn
+// once per FLIP block and each site's coin found without a branch.
+template <int TX, int TY, int TZ, int MODE>
 __device__ __forceinline__ void ising_settle_flip_pass(const RepDesc &d, const RepState &st, int tile, int tid,
                                                        IsingSettleLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
+    constexpr bool ALIGNED = MODE != kFlipGeneral;  // labels staged by local key, every thread has a cell
     int *LAB = S.f.LAB;
     uint32_t *CB = S.f.CB;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
@@ -234,7 +234,7 @@ __device__ __forceinline__ void ising_settle_flip_pass(const RepDesc &d, const R
     int mag = 0;
     if (valid) {
         uint32_t flipmask;
-        if constexpr (ALIGNED) flipmask = cell_flip_mask_aligned<TX, TY, TZ>(lab, LAB, CB, d.lgL);
+        if constexpr (ALIGNED) flipmask = cell_flip_mask_keyed<TX, TY, TZ, MODE>(lab, LAB, CB, d.lgL, ti, cell, tid);
         else flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
         mag = flip_cell(d.spins, cell, flipmask);
     }
@@ -253,11 +253,15 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_settle_flip_ising(Chain c)
     const RepDesc &d = c.desc[rep];
     if constexpr (TX % 8 == 0) {
         if (d.lgL >= 0) {
-            ising_settle_flip_pass<TX, TY, TZ, true>(d, st, blk - d.tile_base, threadIdx.x, S);
+            ising_settle_flip_pass<TX, TY, TZ, kFlipPow2>(d, st, blk - d.tile_base, threadIdx.x, S);
+            return;
+        }
+        if (d.divisible) {
+            ising_settle_flip_pass<TX, TY, TZ, kFlipDivisible>(d, st, blk - d.tile_base, threadIdx.x, S);
             return;
         }
     }
-    ising_settle_flip_pass<TX, TY, TZ, false>(d, st, blk - d.tile_base, threadIdx.x, S);
+    ising_settle_flip_pass<TX, TY, TZ, kFlipGeneral>(d, st, blk - d.tile_base, threadIdx.x, S);
 }
 
 // Records and state: energy partials (state before this sweep) into the

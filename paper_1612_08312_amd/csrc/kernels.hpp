@@ -47,6 +47,7 @@ struct RepDesc {
     // geometry
     int L, ntx, nty, ntz;  // tiles per axis for the chain's tile shape
     int lgL;               // log2 L when L is a power of two that every tile edge divides, else -1
+    int divisible;         // 1 when every tile edge divides L and L >= 2 x the largest edge
     int64_t ncell, N;
     // device buffers owned by the replica
     void *spins;       // int8 [N] or float [n][N]

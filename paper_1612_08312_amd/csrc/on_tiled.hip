@@ -202,13 +202,14 @@ struct OnFlipLds {
 
 // One workgroup per tile, once every unite is done: the settle step
 // (settle_tile_roots), cluster coins from the LDS copy of the tile's labels
-// and the tile's own coins (as in the Ising flip; ALIGNED as there),
+// and the tile's own coins (as in the Ising flip; MODE as there),
 // reflections, FP64 magnetisation.
-template <int NV, int TX, int TY, int TZ, bool ALIGNED>
+template <int NV, int TX, int TY, int TZ, int MODE>
 __device__ __forceinline__ void on_settle_flip_pass(const RepDesc &d, const RepState &st, int tile, int tid,
                                                     OnFlipLds<TX, TY, TZ> &S)
 {
     constexpr int NC = TX * TY * TZ;
+    constexpr bool ALIGNED = MODE != kFlipGeneral;  // labels staged by local key, every thread has a cell
     int *LAB = S.LAB;
     uint32_t *CB = S.CB;
     const TileIdx<TX, TY, TZ> ti = TileIdx<TX, TY, TZ>::of(tile, d);
@@ -235,7 +236,7 @@ __device__ __forceinline__ void on_settle_flip_pass(const RepDesc &d, const RepS
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
         uint32_t flipmask;
-        if constexpr (ALIGNED) flipmask = cell_flip_mask_aligned<TX, TY, TZ>(lab, LAB, CB, d.lgL);
+        if constexpr (ALIGNED) flipmask = cell_flip_mask_keyed<TX, TY, TZ, MODE>(lab, LAB, CB, d.lgL, ti, cell, tid);
         else flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
         float v[NV][16];
 #pragma unroll
@@ -291,11 +292,15 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_settle_flip_on(Chain c)
     const RepDesc &d = c.desc[rep];
     if constexpr (TX % 8 == 0) {
         if (d.lgL >= 0) {
-            on_settle_flip_pass<NV, TX, TY, TZ, true>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+            on_settle_flip_pass<NV, TX, TY, TZ, kFlipPow2>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+            return;
+        }
+        if (d.divisible) {
+            on_settle_flip_pass<NV, TX, TY, TZ, kFlipDivisible>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
             return;
         }
     }
-    on_settle_flip_pass<NV, TX, TY, TZ, false>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
+    on_settle_flip_pass<NV, TX, TY, TZ, kFlipGeneral>(d, st, blockIdx.x - d.tile_base, threadIdx.x, S);
 }
 
 // Records and state (see k_finalize_ising).

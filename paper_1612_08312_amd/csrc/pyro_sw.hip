@@ -409,6 +409,7 @@ RepDesc lattice_desc(int L, int model, double J, uint64_t seed, uint32_t thr_hi,
     d.nty = (L + t.y - 1) / t.y;
     d.ntz = (L + t.z - 1) / t.z;
     d.lgL = -1;
+    d.divisible = L % t.x == 0 && L % t.y == 0 && L % t.z == 0 && L >= 2 * std::max(t.x, std::max(t.y, t.z));
     if ((L & (L - 1)) == 0 && L % t.x == 0 && L % t.y == 0 && L % t.z == 0)
         for (int v = L, k = 0; v > 0; v >>= 1, ++k)
             if (v == 1) d.lgL = k;

@@ -414,22 +414,36 @@ __device__ __forceinline__ int aligned_local_key(int site, int lg)
     return (int)((u & (16u * TX - 1u)) | (ly << (4 + lTX)) | (lz << (4 + lTX + lTY)));
 }
 
-// Flip mask of a flip kernel's cell for an aligned tiling (see
-// aligned_local_key).  LAB holds the tile's labels by local key; CB holds
-// the coin words of the tile's cells, two cells per word as the flip stream
-// draws them (bit (key & 31) of word key >> 5 is the coin of local key
-// `key`).  The same rule as cell_flip_mask: a stored encoding, in the site's
-// own entry or in its local root's, gives the coin; otherwise the local
-// root's own coin.  No branch: both LDS words are read for every site.
-template <int TX, int TY, int TZ>
-__device__ __forceinline__ uint32_t cell_flip_mask_aligned(const int (&lab)[16], const int *LAB, const uint32_t *CB,
-                                                          int lg)
+// How a flip kernel finds a site's local root in its tile: kFlipGeneral
+// stages the labels at lds_pos and decodes with branches (cell_flip_mask);
+// the keyed modes stage them by local key and decode without a branch, for
+// tilings whose tile edges divide L (every thread has a cell, TX >= 8): by
+// bit fields when L is a power of two (kFlipPow2, aligned_local_key), else
+// by rounding the cell offset (kFlipDivisible, TileIdx::local_key_near,
+// exact for L >= 2 x the largest tile edge).
+enum FlipMode : int { kFlipGeneral = 0, kFlipPow2 = 1, kFlipDivisible = 2 };
+
+// Flip mask of a flip kernel's cell for a keyed mode.  LAB holds the
+// tile's labels by local key; CB holds the coin words of the tile's cells,
+// two cells per word as the flip stream draws them (bit (key & 31) of word
+// key >> 5 is the coin of local key `key`).  The same rule as
+// cell_flip_mask: a stored encoding, in the site's own entry or in its
+// local root's, gives the coin; otherwise the local root's own coin.  No
+// branch: both LDS words are read for every site, and the key decoded from
+// an encoding, which is not used, is masked into the tile's key range.
+template <int TX, int TY, int TZ, int MODE>
+__device__ __forceinline__ uint32_t cell_flip_mask_keyed(const int (&lab)[16], const int *LAB, const uint32_t *CB,
+                                                        int lg, const TileIdx<TX, TY, TZ> &ti, int cell, int lcell)
 {
+    constexpr int NC = TX * TY * TZ;
+    static_assert(MODE == kFlipPow2 || MODE == kFlipDivisible, "a keyed mode");
+    static_assert((NC & (NC - 1)) == 0, "tile keys fill a power of two");
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int r = lab[k];
-        const int key = aligned_local_key<TX, TY, TZ>(r, lg);
+        const int key = MODE == kFlipPow2 ? aligned_local_key<TX, TY, TZ>(r, lg)
+                                          : (ti.local_key_near(r, cell, lcell) & (16 * NC - 1));
         const int u = r < 0 ? r : LAB[key];
         const bool enc = u < 0;
         const uint32_t word = enc ? (uint32_t)u : CB[key >> 5];
@@ -438,7 +452,7 @@ __device__ __forceinline__ uint32_t cell_flip_mask_aligned(const int (&lab)[16],
     return mask;
 }
 
-// Coin words of an aligned tile (NC / 8 threads, thread j): local cells
+// Coin words of a keyed tile (NC / 8 threads, thread j): local cells
 // 8j .. 8j + 7 are eight consecutive cells of one x row starting at a
 // multiple of 8 (TX >= 8), i.e. exactly the cells of one FLIP block, whose
 // four words cover two cells each (cell_coins).

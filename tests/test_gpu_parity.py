@@ -224,6 +224,35 @@ def test_on_parity(model, L, T):
     np.testing.assert_allclose(g.spins(), o.spins(), rtol=0, atol=1e-5)
 
 
+@pytest.mark.parametrize("model,L,T,shape", [(1, 24, 4.2139, None), (1, 48, 4.2139, None), (1, 40, 3.0, 3),
+                                             (2, 24, 2.0285, None), (3, 24, 1.31695, None), (2, 48, 2.0285, None)])
+def test_divisible_tilings(model, L, T, shape):
+    """Tile edges that divide a lattice edge that is not a power of two
+    (L = 24 with the default 8x4x4 tiles, L = 48 with 8x8x4, L = 40 with
+    8x8x8): the flip's keyed path that finds a root's local key by rounding
+    the cell offset.  Ising bit-exact; O(n) labels bit-exact, spins within
+    1e-5, records within 1e-5."""
+    say("GPU case:", dict(model=model, L=L, T=T, shape=shape))
+    g = pyrosw.Lattice(L=L, model=model, T=T, seed=13, start=workloads.RANDOM)
+    if shape is not None:
+        g.set_tile_shape(shape)
+    o = oracle.Oracle(L=L, model=model, T=T, seed=13, start=workloads.RANDOM)
+    grec, orec = [], []
+    for _ in range(2):
+        g.sweep(5)
+        grec.append(g.moments())
+        orec.append(o.sweep(5))
+    gr, orr = np.concatenate(grec), np.concatenate(orec)
+    np.testing.assert_array_equal(g.labels(), o.labels())
+    if model == 1:
+        assert_records_exact(gr, orr)
+        np.testing.assert_array_equal(g.spins(), o.spins())
+    else:
+        assert_records_close(gr, orr)
+        np.testing.assert_allclose(g.spins(), o.spins(), rtol=0, atol=1e-5)
+    g.close()
+
+
 def test_on_cold_start_and_infinite_temperature():
     g, o, gr, orr = run_both(3, 3, float("inf"), 2, workloads.COLD, 10)
     assert_records_close(gr, orr)
