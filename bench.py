@@ -56,17 +56,17 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "19f5e09f694700cc"
+COUNTER_FINGERPRINT = "63c1b11b747bb774"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
-    "local": 216841833,
-    "unite": 194593080,
-    "flip": 269822389,
+    "local": 216843216,
+    "unite": 194598739,
+    "flip": 269536135,
     "finalize": 73139,
 }
 MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
-    "local": (60720311, 24649168, 32768),
-    "unite": (11533260, 12804393, 16384),
-    "flip": (25087263, 10713834, 32768),
+    "local": (60720381, 24649122, 32768),
+    "unite": (11533627, 12805128, 16384),
+    "flip": (25214207, 10691965, 32768),
 }
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a

@@ -479,7 +479,7 @@ __device__ __forceinline__ uint4 aligned_coin_words(const TileIdx<TX, TY, TZ> &t
 constexpr int kSettleListPerCell = 4;  // list room per cell; roots beyond it settle in place
 
 // Loads the 16 labels of a flip kernel's cell into lab and copies them into
-// LAB (by local key on an aligned tiling, else at lds_pos).  Returns the
+// LAB (by local key in a keyed FlipMode, else at lds_pos).  Returns the
 // mask of the sites that are hooked local roots; their lab value becomes
 // the site's own index, so that the flip reads the site's settled entry.
 template <int NC, bool ALIGNED>
