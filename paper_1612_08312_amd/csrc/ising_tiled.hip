@@ -41,7 +41,7 @@ template <int TX, int TY, int TZ>
 struct IsingTileLds {
     uint32_t P[kForestSlots<TX * TY * TZ>];     // tile forest
     uint32_t SM[TX * TY * TZ];                  // spin masks of the cells
-    uint32_t U[kUnionsPerCell * TX * TY * TZ];  // union list
+    uint32_t U[kUnionsPerCell<TX * TY * TZ> * TX * TY * TZ];  // union list
     uint8_t K4[64];
     int64_t red[16];
 };

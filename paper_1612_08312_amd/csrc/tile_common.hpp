@@ -629,9 +629,15 @@ __host__ __device__ constexpr uint64_t down_vertex_bytes(int half)
 }
 
 // ------------------------------------------------------ tile components ---
-// Union-list entries per cell of a tile; unions beyond the list are done by
-// the thread that found them.
-constexpr int kUnionsPerCell = 8;
+// Union-list entries per cell of a tile of NC cells; unions beyond the list
+// are done by the thread that found them.  Tiles of 512 cells or more keep
+// one entry per cell: the smaller list lets four 8x8x8 tile workgroups
+// share a CU's LDS instead of three, which pays more than the balance of a
+// longer list (Ising tile pass 598 -> 569 us per launch over five L = 128
+// lattices).  Smaller tiles keep eight: one per cell made L = 48 sweeps
+// with 8x8x4 tiles 3-4% slower.
+template <int NC>
+constexpr int kUnionsPerCell = NC >= 512 ? 1 : 8;
 
 // Second half of both models' tile pass (every thread of the block calls
 // it; `act` is 0 for threads without a cell, lc[] holds the local index of
@@ -662,7 +668,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 {
     constexpr int NC = TX * TY * TZ;
     static_assert(NC % 64 == 0, "tiles are whole waves");
-    constexpr int kCap = kUnionsPerCell * NC - NC / 64;  // union list; its wave totals follow it in U
+    constexpr int kCap = kUnionsPerCell<NC> * NC - NC / 64;  // union list; its wave totals follow it in U
     uint32_t *WT = U + kCap;
     // local key of vertex mu of down tetrahedron f (-1 when outside the tile)
     auto vkey = [&](int f, int mu) {
