@@ -41,7 +41,7 @@ template <int TX, int TY, int TZ>
 struct IsingTileLds {
     uint32_t P[kForestSlots<TX * TY * TZ>];     // tile forest
     uint32_t SM[TX * TY * TZ];                  // spin masks of the cells
-    uint32_t U[kUnionsPerCell<TX * TY * TZ> * TX * TY * TZ];  // union list
+    uint32_t U[kIsingUnionsPerCell<TX * TY * TZ> * TX * TY * TZ];  // union list
     uint8_t K4[64];
     int64_t red[16];
 };
@@ -114,7 +114,7 @@ __device__ __forceinline__ void ising_tile_pass(const RepDesc &d, const RepState
         aligned_count = (int)__popcll(al);
         act = ising_activate(al, (uint32_t)cell, st.t, d.key, IsingParams{d.thr_hi, d.thr_lo});
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4);
+    tile_components<TX, TY, TZ, kIsingUnionsPerCell<NC>>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, SM, K4);
     const int64_t bsum = block_sum<int64_t, !kLast>(valid ? (int64_t)(2 * aligned_count - nbonds) : 0, red);
     if (tid == 0) d.ipart[tile] = bsum;
 }

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
     __shared__ uint32_t P[kForestSlots<NC>];
-    __shared__ uint32_t U[kUnionsPerCell<NC> * NC];
+    __shared__ uint32_t U[kOnUnionsPerCell * NC];
     __shared__ uint32_t DA[NC];
     __shared__ uint8_t K4[64];
     __shared__ double red[16];
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
             }
         }
     }
-    tile_components<TX, TY, TZ>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, DA, K4);
+    tile_components<TX, TY, TZ, kOnUnionsPerCell>(d, ti, tile, tid, lcid, valid, cell, act, lc, P, U, DA, K4);
     const double b = block_sum<double, false>(esum, red);
     if (tid == 0) d.dpart[tile] = b;
 }

@@ -629,15 +629,18 @@ __host__ __device__ constexpr uint64_t down_vertex_bytes(int half)
 }
 
 // ------------------------------------------------------ tile components ---
-// Union-list entries per cell of a tile of NC cells; unions beyond the list
-// are done by the thread that found them.  Tiles of 512 cells or more keep
-// one entry per cell: the smaller list lets four 8x8x8 tile workgroups
-// share a CU's LDS instead of three, which pays more than the balance of a
-// longer list (Ising tile pass 598 -> 569 us per launch over five L = 128
-// lattices).  Smaller tiles keep eight: one per cell made L = 48 sweeps
-// with 8x8x4 tiles 3-4% slower.
+// Union-list entries per cell of a tile of NC cells (the UPC argument of
+// tile_components); unions beyond the list are done by the thread that
+// found them.  The Ising tile pass keeps one entry per cell for tiles of
+// 512 cells or more: the smaller list lets four 8x8x8 tile workgroups share
+// a CU's LDS instead of three, which pays more than the balance of a longer
+// list (tile pass 598 -> 569 us per launch over five L = 128 lattices).
+// Its smaller tiles keep eight (one per cell made L = 48 sweeps with 8x8x4
+// tiles 3-4% slower), and so does the O(n) tile pass, whose 8x8x8 tiles
+// were 3-4% slower with one.
 template <int NC>
-constexpr int kUnionsPerCell = NC >= 512 ? 1 : 8;
+constexpr int kIsingUnionsPerCell = NC >= 512 ? 1 : 8;
+constexpr int kOnUnionsPerCell = 8;
 
 // Second half of both models' tile pass (every thread of the block calls
 // it; `act` is 0 for threads without a cell, lc[] holds the local index of
@@ -660,7 +663,7 @@ constexpr int kUnionsPerCell = NC >= 512 ? 1 : 8;
 // whose name differs are emitted: at most 3 pairs per tetrahedron, none
 // repeated.  These tetrahedra belong to the cells of the low faces; they
 // are handed out to all threads as a table of (cell, tetrahedron) items.
-template <int TX, int TY, int TZ>
+template <int TX, int TY, int TZ, int UPC>
 __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<TX, TY, TZ> &ti, int tile, int tid,
                                                 int lcid, bool valid, int cell, uint64_t act,
                                                 const int (&lc)[kNCellCodes], uint32_t *P, uint32_t *U, uint32_t *DA,
@@ -668,7 +671,7 @@ __device__ __forceinline__ void tile_components(const RepDesc &d, const TileIdx<
 {
     constexpr int NC = TX * TY * TZ;
     static_assert(NC % 64 == 0, "tiles are whole waves");
-    constexpr int kCap = kUnionsPerCell<NC> * NC - NC / 64;  // union list; its wave totals follow it in U
+    constexpr int kCap = UPC * NC - NC / 64;  // union list; its wave totals follow it in U
     uint32_t *WT = U + kCap;
     // local key of vertex mu of down tetrahedron f (-1 when outside the tile)
     auto vkey = [&](int f, int mu) {
