@@ -29,7 +29,9 @@ def both(L, model, T, seed, vacancy, sweeps):
     return g, o, g.moments(), o.sweep(sweeps), s0
 
 
-@pytest.mark.parametrize("L,vacancy", [(4, 0.1), (5, 0.5), (7, 0.25), (2, 1.0)])
+# L = 16 and 24 take the flip's keyed paths (8x4x4 tiles dividing L: bit
+# fields for the power of two, the rounding decode for 24)
+@pytest.mark.parametrize("L,vacancy", [(4, 0.1), (5, 0.5), (7, 0.25), (2, 1.0), (16, 0.1), (24, 0.2)])
 def test_diluted_ising_bit_exact(L, vacancy):
     g, o, gr, orr, s0 = both(L, 1, 4.0, 300 + L, vacancy, 120)
     for f in ("sweep", "bond_sum", "M_int", "E", "m2", "m4"):
@@ -42,7 +44,7 @@ def test_diluted_ising_bit_exact(L, vacancy):
     g.close()
 
 
-@pytest.mark.parametrize("model,L", [(2, 4), (3, 5)])
+@pytest.mark.parametrize("model,L", [(2, 4), (3, 5), (2, 24)])
 def test_diluted_on_parity(model, L):
     T = workloads.TC[model]
     g, o, gr, orr, s0 = both(L, model, T, 400 + L, 0.2, 60)
