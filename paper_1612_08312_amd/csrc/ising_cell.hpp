@@ -27,16 +27,24 @@ struct IsingParams {
     uint32_t thr_lo;
 };
 
+// Byte flags of four words (each byte 0x80 when set, 0 otherwise) -> 16 bits,
+// bit 4k + b = the flag of byte b of word k.  v_dot4_u32_u8 sums the four
+// byte products with the weights 2^b (word 0, 2) or 2^(b+4) (word 1, 3), so
+// each pair of words lands as a byte shifted left by 7: full-rate dot
+// instructions instead of quarter-rate multiplies.
+__device__ __forceinline__ uint32_t gather_flags16(uint32_t f0, uint32_t f1, uint32_t f2, uint32_t f3)
+{
+    const uint32_t lo = __builtin_amdgcn_udot4(f1, 0x80402010u, __builtin_amdgcn_udot4(f0, 0x08040201u, 0u, false), false);
+    const uint32_t hi = __builtin_amdgcn_udot4(f3, 0x80402010u, __builtin_amdgcn_udot4(f2, 0x08040201u, 0u, false), false);
+    return (lo >> 7) | (hi << 1);
+}
+
 // 16 int8 spins (+1 = 0x01, -1 = 0xFF) -> 16-bit mask, bit k set when spin k
-// is -1.  The multiply gathers the four byte sign bits of a word into bits
-// 28..31 (partial products never overlap there).
+// is -1 (the byte's sign bit).
 __device__ __forceinline__ uint32_t spin_mask16(int4 v)
 {
-    const uint32_t w[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
-    uint32_t m = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) m |= (((w[k] & 0x80808080u) * 0x00204081u) >> 28) << (4 * k);
-    return m;
+    return gather_flags16((uint32_t)v.x & 0x80808080u, (uint32_t)v.y & 0x80808080u, (uint32_t)v.z & 0x80808080u,
+                          (uint32_t)v.w & 0x80808080u);
 }
 
 // Mask of the 16 down-tetrahedron vertices, bit 4f + mu = vertex mu of the
@@ -92,21 +100,19 @@ __device__ __forceinline__ uint64_t aligned48(uint32_t m, uint32_t dm)
 }
 
 // Per-byte flags of four bytes x against one byte value c (replicated in C):
-// x < c and x == c, each as a 4-bit nibble (bit b for byte b).
-__device__ __forceinline__ uint32_t nibble_of_msbs(uint32_t f) { return ((f & 0x80808080u) * 0x00204081u) >> 28; }
-
+// x < c and x == c, as 0x80 in each byte where the comparison holds.
 __device__ __forceinline__ uint32_t bytes_lt(uint32_t x, uint32_t C)
 {
     // d: top bit of each byte = (x mod 128) >= (c mod 128), no cross-byte borrow
     const uint32_t d = (x | 0x80808080u) - (C & 0x7F7F7F7Fu);
-    return nibble_of_msbs((~x & C) | (~(x ^ C) & ~d));
+    return ((~x & C) | (~(x ^ C) & ~d)) & 0x80808080u;
 }
 
 __device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t C)
 {
     const uint32_t t = x ^ C;
     const uint32_t nz = ((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t;
-    return nibble_of_msbs(~nz);
+    return ~nz & 0x80808080u;
 }
 
 // Active bonds of cell `cell` in sweep t, given its aligned-bond mask.
@@ -119,16 +125,15 @@ __device__ __forceinline__ uint64_t ising_activate(uint64_t aligned, uint32_t ce
         acc = ~0ull;
     } else {
         const uint32_t C = p.thr_hi * 0x01010101u;
+        uint32_t lt[3], eq[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const uint4 r = philox4x32_10(3u * cell + q, t, kStreamBond, 0u, key);
-            const uint32_t w[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                acc |= (uint64_t)bytes_lt(w[k], C) << (16 * q + 4 * k);
-                tie |= (uint64_t)bytes_eq(w[k], C) << (16 * q + 4 * k);
-            }
+            lt[q] = gather_flags16(bytes_lt(r.x, C), bytes_lt(r.y, C), bytes_lt(r.z, C), bytes_lt(r.w, C));
+            eq[q] = gather_flags16(bytes_eq(r.x, C), bytes_eq(r.y, C), bytes_eq(r.z, C), bytes_eq(r.w, C));
         }
+        acc = (uint64_t)(lt[0] | lt[1] << 16) | (uint64_t)lt[2] << 32;
+        tie = (uint64_t)(eq[0] | eq[1] << 16) | (uint64_t)eq[2] << 32;
     }
     uint64_t act = aligned & acc;
     uint64_t amb = aligned & tie;
