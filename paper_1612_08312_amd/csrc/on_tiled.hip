@@ -49,8 +49,12 @@ __global__ void k_axis(Chain c)
 }
 
 
+// Four waves per SIMD, so at most 128 VGPRs: left alone, the Heisenberg pass
+// takes 139 and only three 8x8x4 workgroups share a CU (60 -> 51 us per
+// L = 64 sweep with the cap, despite a few spills).  XY takes 113 either way;
+// a cap of five waves made its pass slower (43 -> 48 us).
 template <int NV, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX *TY *TZ) void k_local_on(Chain c)
+__global__ __launch_bounds__(TX *TY *TZ) __attribute__((amdgpu_waves_per_eu(4))) void k_local_on(Chain c)
 {
     constexpr int NC = TX * TY * TZ;
     __shared__ uint32_t P[kForestSlots<NC>];
