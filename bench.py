@@ -56,17 +56,17 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "314d5a0c306026eb"
+COUNTER_FINGERPRINT = "ef77e3172b825757"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
-    "local": 216829792,
-    "unite": 194592662,
-    "flip": 269542042,
-    "finalize": 73139,
+    "local": 216858788,
+    "unite": 194592587,
+    "flip": 269565972,
+    "finalize": 73136,
 }
 MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
-    "local": (64363117, 28660103, 32768),
-    "unite": (11532716, 12804067, 16384),
-    "flip": (25214518, 10692272, 32768),
+    "local": (62134578, 28267216, 32768),
+    "unite": (11532950, 12804266, 16384),
+    "flip": (24888953, 10496177, 32768),
 }
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a
