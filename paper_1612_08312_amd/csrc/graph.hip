@@ -2,11 +2,11 @@
 // table): the paper's remark that the algorithm carries over to other
 // lattices once a nearest-neighbour table is supplied (Sec. 2, Sec. 4).
 //
-// No lattice tiles: windows of consecutive site indices, and one thread per
-// bond or per site.  Per sweep:
+// No lattice tiles: windows of 4096 sites, and one thread per bond or per
+// site.  Per sweep:
 //   O(n) only  k_graph_axis       embedding axis of the sweep (one thread)
 //   O(n) only  k_graph_prepare    sigma_i = s_i . r
-//              k_graph_local      sites cut into windows of 4096 indices, one
+//              k_graph_local      sites cut into windows of 4096, one
 //                                 workgroup each: activation of the bonds with
 //                                 both ends in the window and their union in
 //                                 LDS; every site stores its local root
@@ -60,6 +60,9 @@ struct GraphDesc {
                              // then the bonds between windows
     const uint32_t *bond_id; // position of each bond in the caller's table (keys its draws)
     const int64_t *wstart;   // [nwin + 1] first bond of each window; wstart[nwin] = first bond between windows
+    const int32_t *wsite;    // [N] window w holds the sites wsite[w kWindow ..], ascending within the
+                             // window; NULL: window w holds the indices w kWindow ..
+    const uint16_t *la, *lb; // bonds inside a window: positions of their ends in the window
     void *spins;  // int8 [N] or float [n][N]
     int32_t *label;
     float *sigma;  // O(n) projections [N]
@@ -179,8 +182,10 @@ __device__ __forceinline__ void add_bond_sum(const GraphDesc &g, int64_t e, int6
         __hip_atomic_fetch_add(g.eacc, (unsigned long long)bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sites are cut into windows of kWindow consecutive indices; bonds are
-// grouped (at set-up) by the window of their first end.
+// Sites are cut into windows of kWindow sites (the last may hold fewer):
+// either consecutive indices, or, where that cuts fewer bonds, balls grown
+// breadth first over the bond table (set-up, graph_windows).  Bonds with
+// both ends in one window are grouped (at set-up) by window.
 constexpr int kWindow = 4096;
 constexpr int kLocalThreads = 512;  // threads of the window pass
 
@@ -204,17 +209,18 @@ __global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint
     __shared__ int64_t red[16];
     const int64_t base = (int64_t)blockIdx.x * kWindow;
     const int nloc = (int)std::min<int64_t>(kWindow, g.N - base);
+    const int32_t *ws = g.wsite ? g.wsite + base : nullptr;  // uniform
     for (int k = threadIdx.x; k < nloc; k += kLocalThreads) {
+        const int64_t i = ws ? (int64_t)ws[k] : base + k;
         P[k] = k;
-        SG[k] = g.n == 1 ? (float)((const int8_t *)g.spins)[base + k] : g.sigma[base + k];
+        SG[k] = g.n == 1 ? (float)((const int8_t *)g.spins)[i] : g.sigma[i];
     }
     __syncthreads();
     const int64_t b1 = g.wstart[blockIdx.x + 1];
     int64_t e = 0;
     for (int64_t q = g.wstart[blockIdx.x] + threadIdx.x; q < b1; q += kLocalThreads) {
-        const int32_t i = g.ba[q], j = g.bb[q];
-        if (j < base || j >= base + nloc) continue;  // never: set-up puts such bonds in the cross list
-        const float vi = SG[i - base], vj = SG[j - base];
+        int a = g.la[q], b = g.lb[q];
+        const float vi = SG[a], vj = SG[b];
         const uint32_t bid = g.bond_id[q];
         bool active;
         if (g.n == 1) {
@@ -227,7 +233,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint
             active = on_bond_active(x, word_of(w, bid & 3u));
         }
         if (!active) continue;
-        int a = (int)(i - base), b = (int)(j - base);
         for (;;) {
             a = lds_root(P, a);
             b = lds_root(P, b);
@@ -243,7 +248,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_graph_local(GraphDesc g, uint
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nloc; k += kLocalThreads) g.label[base + k] = (int32_t)(base + lds_root(P, k));
+    // Positions ascend with site index inside a window, so the smallest
+    // position of a component is its smallest site.
+    for (int k = threadIdx.x; k < nloc; k += kLocalThreads) {
+        const int r = lds_root(P, k);
+        if (ws)
+            g.label[ws[k]] = ws[r];
+        else
+            g.label[base + k] = (int32_t)(base + r);
+    }
     add_bond_sum(g, e, red);
 }
 
@@ -499,6 +512,85 @@ int graph_drain(pyro_sw_graph *g)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Windows as balls grown breadth first over the bond table: window w takes
+// sites in breadth-first order from the smallest site not yet taken until it
+// holds kWindow sites (a component that runs out continues from the next
+// smallest free site), so every window but the last is full.  On a lattice
+// numbered row by row, consecutive indices make thin slabs whose faces cut
+// many bonds (a third of the simple cubic's at L = 256); balls cut about a
+// third as many.  The balls are kept only when they cut fewer bonds than
+// consecutive windows.  Then wsite lists each window's sites in ascending
+// order, win gives each site's window and pos its position in it; otherwise
+// all three are left empty.  Windows change the work split only: labels are
+// canonical and every draw is keyed by bond, site and sweep.
+void graph_windows(int64_t N, int64_t NB, const int32_t *ba, const int32_t *bb, std::vector<int32_t> &wsite,
+                   std::vector<int32_t> &win, std::vector<uint16_t> &pos)
+{
+    if (N <= kWindow || NB == 0) return;
+    std::vector<int32_t> order;
+    {
+        std::vector<int64_t> off((size_t)N + 1, 0);
+        for (int64_t k = 0; k < NB; ++k) {
+            ++off[(size_t)ba[k] + 1];
+            ++off[(size_t)bb[k] + 1];
+        }
+        for (int64_t i = 0; i < N; ++i) off[(size_t)i + 1] += off[(size_t)i];
+        std::vector<int32_t> adj((size_t)(2 * NB));
+        {
+            std::vector<int64_t> cur(off.begin(), off.end() - 1);
+            for (int64_t k = 0; k < NB; ++k) {
+                adj[(size_t)cur[(size_t)ba[k]]++] = bb[k];
+                adj[(size_t)cur[(size_t)bb[k]]++] = ba[k];
+            }
+        }
+        win.assign((size_t)N, -1);
+        order.reserve((size_t)N);
+        std::vector<int32_t> queue;
+        queue.reserve(kWindow);
+        int32_t w = 0;
+        int fill = 0;
+        int64_t next = 0;
+        auto take = [&](int32_t x) {  // true when the window is full
+            win[(size_t)x] = w;
+            order.push_back(x);
+            if (++fill < kWindow) return false;
+            ++w;
+            fill = 0;
+            return true;
+        };
+        while ((int64_t)order.size() < N) {
+            while (win[(size_t)next] >= 0) ++next;
+            queue.clear();
+            queue.push_back((int32_t)next);
+            bool full = take((int32_t)next);
+            for (size_t h = 0; !full && h < queue.size(); ++h) {
+                const int32_t x = queue[h];
+                for (int64_t j = off[(size_t)x]; j < off[(size_t)x + 1] && !full; ++j) {
+                    const int32_t y = adj[(size_t)j];
+                    if (win[(size_t)y] < 0) {
+                        queue.push_back(y);
+                        full = take(y);
+                    }
+                }
+            }
+        }
+    }
+    int64_t cut_balls = 0, cut_runs = 0;
+    for (int64_t k = 0; k < NB; ++k) {
+        cut_balls += win[(size_t)ba[k]] != win[(size_t)bb[k]];
+        cut_runs += ba[k] / kWindow != bb[k] / kWindow;
+    }
+    if (cut_balls >= cut_runs) {
+        win.clear();
+        return;
+    }
+    for (int64_t w0 = 0; w0 < N; w0 += kWindow)
+        std::sort(order.begin() + w0, order.begin() + std::min<int64_t>(N, w0 + kWindow));
+    pos.resize((size_t)N);
+    for (int64_t q = 0; q < N; ++q) pos[(size_t)order[(size_t)q]] = (uint16_t)(q % kWindow);
+    wsite.swap(order);
+}
+
 }  // namespace
 
 extern "C" {
@@ -529,32 +621,53 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     const size_t spin_bytes = model == PYRO_ISING ? (size_t)n_sites : sizeof(float) * model * (size_t)n_sites;
     // Bonds inside one window first, grouped by window (stable counting
     // sort), then the bonds between windows in table order; bond_id keeps
-    // each one's position in the caller's table.
+    // each one's position in the caller's table, and la / lb the positions of
+    // an inside bond's ends in its window.
     const int64_t nwin = (n_sites + kWindow - 1) / kWindow;
+    std::vector<int32_t> wsite, win;
+    std::vector<uint16_t> pos;
+    graph_windows(n_sites, n_bonds, bond_a, bond_b, wsite, win, pos);
+    const bool balls = !wsite.empty();
+    auto wof = [&](int32_t i) -> int64_t { return balls ? (int64_t)win[(size_t)i] : (int64_t)(i / kWindow); };
+    auto pof = [&](int32_t i) -> uint16_t { return balls ? pos[(size_t)i] : (uint16_t)(i % kWindow); };
     std::vector<int64_t> wstart((size_t)nwin + 1, 0);
     std::vector<int32_t> ga((size_t)n_bonds), gb((size_t)n_bonds);
     std::vector<uint32_t> gid((size_t)n_bonds);
-    auto inside = [&](int64_t k) { return bond_a[k] / kWindow == bond_b[k] / kWindow; };
+    auto inside = [&](int64_t k) { return wof(bond_a[k]) == wof(bond_b[k]); };
     for (int64_t k = 0; k < n_bonds; ++k)
-        if (inside(k)) ++wstart[(size_t)(bond_a[k] / kWindow) + 1];
+        if (inside(k)) ++wstart[(size_t)wof(bond_a[k]) + 1];
     for (int64_t w = 0; w < nwin; ++w) wstart[(size_t)w + 1] += wstart[(size_t)w];
+    const int64_t n_inside = wstart[(size_t)nwin];
+    std::vector<uint16_t> hla((size_t)n_inside), hlb((size_t)n_inside);
     {
         std::vector<int64_t> cur(wstart.begin(), wstart.end() - 1);
-        int64_t cross = wstart[(size_t)nwin];
+        int64_t cross = n_inside;
         for (int64_t k = 0; k < n_bonds; ++k) {
-            const int64_t q = inside(k) ? cur[(size_t)(bond_a[k] / kWindow)]++ : cross++;
+            const bool in = inside(k);
+            const int64_t q = in ? cur[(size_t)wof(bond_a[k])]++ : cross++;
             ga[(size_t)q] = bond_a[k];
             gb[(size_t)q] = bond_b[k];
             gid[(size_t)q] = (uint32_t)k;
+            if (in) {
+                hla[(size_t)q] = pof(bond_a[k]);
+                hlb[(size_t)q] = pof(bond_b[k]);
+            }
         }
     }
-    size_t off[12], total = 0;
-    const size_t sizes[12] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
-                              sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
-                              16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
-                              sizeof(DevRecord) * (kGraphRing + 1), sizeof(uint32_t) * (size_t)n_bonds,
-                              sizeof(int64_t) * (size_t)(nwin + 1), sizeof(unsigned long long)};
-    for (int k = 0; k < 12; ++k) {
+    win.clear();
+    win.shrink_to_fit();
+    pos.clear();
+    pos.shrink_to_fit();
+    constexpr int kParts = 15;
+    size_t off[kParts], total = 0;
+    const size_t sizes[kParts] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
+                                  sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
+                                  16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
+                                  sizeof(DevRecord) * (kGraphRing + 1), sizeof(uint32_t) * (size_t)n_bonds,
+                                  sizeof(int64_t) * (size_t)(nwin + 1), sizeof(unsigned long long),
+                                  sizeof(int32_t) * wsite.size(), sizeof(uint16_t) * (size_t)n_inside,
+                                  sizeof(uint16_t) * (size_t)n_inside};
+    for (int k = 0; k < kParts; ++k) {
         off[k] = total;
         total += align256(sizes[k]);
     }
@@ -578,7 +691,7 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     GraphDesc &d = g->d;
     d.N = n_sites;
     d.NB = n_bonds;
-    d.n_cross = n_bonds - wstart[(size_t)nwin];
+    d.n_cross = n_bonds - n_inside;
     d.n = model;
     d.ba = (const int32_t *)(g->mem + off[0]);
     d.bb = (const int32_t *)(g->mem + off[1]);
@@ -592,11 +705,20 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     d.bond_id = (const uint32_t *)(g->mem + off[9]);
     d.wstart = (const int64_t *)(g->mem + off[10]);
     d.eacc = (unsigned long long *)(g->mem + off[11]);
+    d.wsite = balls ? (const int32_t *)(g->mem + off[12]) : nullptr;
+    d.la = (const uint16_t *)(g->mem + off[13]);
+    d.lb = (const uint16_t *)(g->mem + off[14]);
     d.J = J;
     d.key = philox_key(seed);
     graph_params(g, T);
     hipError_t e = hipMemcpy((void *)d.wstart, wstart.data(), sizeof(int64_t) * wstart.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(d.eacc, 0, sizeof(unsigned long long));
+    if (e == hipSuccess && balls)
+        e = hipMemcpy((void *)d.wsite, wsite.data(), sizeof(int32_t) * wsite.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_inside > 0)
+        e = hipMemcpy((void *)d.la, hla.data(), sizeof(uint16_t) * (size_t)n_inside, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_inside > 0)
+        e = hipMemcpy((void *)d.lb, hlb.data(), sizeof(uint16_t) * (size_t)n_inside, hipMemcpyHostToDevice);
     if (n_bonds > 0) {
         if (e == hipSuccess)
             e = hipMemcpy((void *)d.ba, ga.data(), sizeof(int32_t) * (size_t)n_bonds, hipMemcpyHostToDevice);
