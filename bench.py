@@ -56,17 +56,17 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "ae4ca91f75cf7f3e"
+COUNTER_FINGERPRINT = "368b491569fec74b"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
-    "local": 216857598,
-    "unite": 194588147,
-    "flip": 269563042,
+    "local": 216853922,
+    "unite": 194594826,
+    "flip": 269551370,
     "finalize": 73136,
 }
 MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
-    "local": (62134488, 28267163, 32768),
-    "unite": (11533495, 12804483, 16384),
-    "flip": (24888143, 10495365, 32768),
+    "local": (62134735, 28267650, 32768),
+    "unite": (11533246, 12804243, 16384),
+    "flip": (24888933, 10496153, 32768),
 }
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a
