@@ -626,7 +626,13 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     const int64_t nwin = (n_sites + kWindow - 1) / kWindow;
     std::vector<int32_t> wsite, win;
     std::vector<uint16_t> pos;
-    graph_windows(n_sites, n_bonds, bond_a, bond_b, wsite, win, pos);
+    try {
+        graph_windows(n_sites, n_bonds, bond_a, bond_b, wsite, win, pos);
+    } catch (const std::bad_alloc &) {  // no host memory for the balls: consecutive windows
+        wsite.clear();
+        win.clear();
+        pos.clear();
+    }
     const bool balls = !wsite.empty();
     auto wof = [&](int32_t i) -> int64_t { return balls ? (int64_t)win[(size_t)i] : (int64_t)(i / kWindow); };
     auto pof = [&](int32_t i) -> uint16_t { return balls ? pos[(size_t)i] : (uint16_t)(i % kWindow); };
