@@ -14,7 +14,7 @@ namespace pyro {
 
 const char *kernel_name(int id)
 {
-    static const char *names[kNumKernels] = {"init", "local", "unite", "flip", "energy", "finalize", "axis", "persist", "resident"};
+    static const char *names[kNumKernels] = {"init", "local", "unite", "flip", "energy", "finalize", "persist", "resident"};
     return (id >= 0 && id < kNumKernels) ? names[id] : "?";
 }
 

@@ -54,7 +54,6 @@ struct RepDesc {
     int32_t *label;    // [N]
     int64_t *ipart;    // integer partial sums
     double *dpart;     // FP64 partial sums
-    float *axis;       // [4] embedding axis of the current sweep
     DevRecord *ring;   // per-sweep records
     int *pairs;        // per-tile crossing lists: pair count, root count (set by the unite pass), then
                        // (name, name) pairs, replaced by the distinct local roots when the root count is > 0
@@ -102,7 +101,6 @@ enum KernelId : int {
     kKFlip,      // settle and flip
     kKEnergy,    // energy tail
     kKFinalize,
-    kKAxis,      // O(n) axis
     kKPersist,   // persistent fused sweep (all sweeps of a call)
     kKResident,  // LDS-resident small lattices (all sweeps of a call)
     kNumKernels

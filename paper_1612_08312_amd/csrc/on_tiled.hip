@@ -33,19 +33,17 @@
 
 namespace pyro {
 
-// Embedding axis of the next sweep of every active replica (one thread each).
-__global__ void k_axis(Chain c)
+// Embedding axis of sweep t.  Both passes that use it draw it themselves:
+// the inputs are uniform, so every lane computes the same value, at the cost
+// of a few dozen instructions per wave instead of a kernel of its own (about
+// 6 us per sweep, most of it launch latency).
+template <int NV>
+__device__ __forceinline__ void sweep_axis(const RepDesc &d, uint32_t t, float (&r)[NV])
 {
-    const int rep = blockIdx.x;
-    const RepState st = *c.state[rep];
-    if (threadIdx.x != 0 || st.remaining <= 0) return;
-    const RepDesc &d = c.desc[rep];
-    float r[3];
-    unit_vector(0u, st.t, kStreamAxis, c.model, d.key, r);
-    d.axis[0] = r[0];
-    d.axis[1] = r[1];
-    d.axis[2] = r[2];
-    d.axis[3] = 0.0f;
+    float a[3];
+    unit_vector(0u, t, kStreamAxis, NV, d.key, a);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) r[k] = a[k];
 }
 
 
@@ -145,8 +143,7 @@ __global__ __launch_bounds__(TX *TY *TZ) __attribute__((amdgpu_waves_per_eu(4)))
     }
     if (valid) {
         float r[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
+        sweep_axis<NV>(d, st.t, r);
         float sig_own[16], sig_dv[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -237,8 +234,7 @@ __device__ __forceinline__ void on_settle_flip_pass(const RepDesc &d, const RepS
     for (int k = 0; k < NV; ++k) M[k] = 0.0;
     if (valid) {
         float r[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) r[k] = d.axis[k];
+        sweep_axis<NV>(d, st.t, r);
         uint32_t flipmask;
         if constexpr (ALIGNED) flipmask = cell_flip_mask_keyed<TX, TY, TZ, MODE>(lab, LAB, CB, d.lgL, ti, cell, tid);
         else flipmask = cell_flip_mask<NC>(lab, LAB, CB, ti, cell, tid, st.t, d.key);
@@ -423,7 +419,6 @@ struct OnFlip {
 template <int NV>
 static hipError_t sweep_on(const Chain &c, hipStream_t st, const LaunchHook &hook)
 {
-    PYRO_LAUNCH(kKAxis, k_axis, c.nreps, 64, c);
     hipError_t e = with_tile_shape<OnLocal<NV>>(c.shape, c, st, hook);
     if (e == hipSuccess) e = launch_unite(c, st, hook);
     if (e == hipSuccess) e = with_tile_shape<OnFlip<NV>>(c.shape, c, st, hook);

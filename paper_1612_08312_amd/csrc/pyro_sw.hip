@@ -128,7 +128,7 @@ int64_t max_tiles(int L)
 
 struct Layout {
     size_t spin_bytes;
-    size_t label, ipart, dpart, axis, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
+    size_t label, ipart, dpart, ring, pairs, state, solo_desc, solo_stp, solo_map, total;
     int64_t map_len;
 };
 
@@ -147,7 +147,6 @@ Layout layout_for(int L, int model)
     ly.label = take(sizeof(int32_t) * (size_t)N);
     ly.ipart = take(sizeof(int64_t) * (size_t)ipart_count(L));
     ly.dpart = take(model == PYRO_ISING ? 0 : sizeof(double) * (size_t)dpart_count(L));
-    ly.axis = take(4 * sizeof(float));
     ly.ring = take(sizeof(pyro_sw_record) * (size_t)kRing);
     ly.pairs = take(sizeof(int) * (size_t)pair_list_ints(L));
     ly.state = take(sizeof(RepState));
@@ -419,7 +418,6 @@ RepDesc lattice_desc(int L, int model, double J, uint64_t seed, uint32_t thr_hi,
     d.label = (int32_t *)(work + ly.label);
     d.ipart = (int64_t *)(work + ly.ipart);
     d.dpart = model == PYRO_ISING ? nullptr : (double *)(work + ly.dpart);
-    d.axis = (float *)(work + ly.axis);
     d.ring = (DevRecord *)(work + ly.ring);
     d.pairs = (int *)(work + ly.pairs);
     d.list_stride = tile_list_stride(shape);
