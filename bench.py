@@ -56,17 +56,17 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "5413cae1793f968e"
+COUNTER_FINGERPRINT = "2cd9442a7c733d60"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
-    "local": 216856930,
-    "unite": 194598689,
-    "flip": 269555197,
+    "local": 216860251,
+    "unite": 194595608,
+    "flip": 269571215,
     "finalize": 73139,
 }
 MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
-    "local": (62134660, 28267487, 32768),
-    "unite": (11533549, 12804995, 16384),
-    "flip": (24889189, 10496410, 32768),
+    "local": (62134656, 28267301, 32768),
+    "unite": (11533229, 12804377, 16384),
+    "flip": (24888704, 10495926, 32768),
 }
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a

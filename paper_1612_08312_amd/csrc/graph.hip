@@ -4,8 +4,8 @@
 //
 // No lattice tiles: windows of 4096 sites, and one thread per bond or per
 // site.  Per sweep:
-//   O(n) only  k_graph_axis       embedding axis of the sweep (one thread)
-//   O(n) only  k_graph_prepare    sigma_i = s_i . r
+//   O(n) only  k_graph_prepare    sigma_i = s_i . r (each workgroup draws the
+//                                 sweep's embedding axis r itself)
 //              k_graph_local      sites cut into windows of 4096, one
 //                                 workgroup each: activation of the bonds with
 //                                 both ends in the window and their union in
@@ -66,7 +66,6 @@ struct GraphDesc {
     void *spins;  // int8 [N] or float [n][N]
     int32_t *label;
     float *sigma;  // O(n) projections [N]
-    float *axis;   // [4]
     int64_t *ipart;  // Ising partials: [kPartBlocks bond blocks][kPartBlocks site blocks]
     double *dpart;   // O(n) partials: [kPartBlocks bond blocks][3][kPartBlocks site blocks]
     DevRecord *ring;
@@ -122,23 +121,23 @@ __device__ __forceinline__ uint32_t coin_of(int32_t r, uint32_t t, PhiloxKey key
     return (word_of(w, ((uint32_t)r >> 5) & 3u) >> (r & 31)) & 1u;
 }
 
-__global__ void k_graph_axis(GraphDesc g, uint32_t t)
+// Embedding axis of sweep t into LDS, drawn by the workgroup's first thread
+// (a kernel of its own for it cost a launch per sweep).  Every thread of
+// the workgroup must call it.
+__device__ __forceinline__ void graph_axis(const GraphDesc &g, uint32_t t, float *ax)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float r[3];
-    unit_vector(0u, t, kStreamAxis, g.n, g.key, r);
-    g.axis[0] = r[0];
-    g.axis[1] = r[1];
-    g.axis[2] = r[2];
-    g.axis[3] = 0.0f;
+    if (threadIdx.x == 0) unit_vector(0u, t, kStreamAxis, g.n, g.key, ax);
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_graph_prepare(GraphDesc g)
+__global__ __launch_bounds__(kBlock) void k_graph_prepare(GraphDesc g, uint32_t t)
 {
+    __shared__ float ax[3];
+    graph_axis(g, t, ax);
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.N) return;
     const float *s = (const float *)g.spins;
-    const float r[3] = {g.axis[0], g.axis[1], g.axis[2]};
+    const float r[3] = {ax[0], ax[1], ax[2]};
     const float v[3] = {s[i], s[g.N + i], g.n == 3 ? s[2 * g.N + i] : 0.0f};
     g.sigma[i] = g.n == 2 ? project<2>(v, r) : project<3>(v, r);
 }
@@ -287,6 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t)
 {
     __shared__ int64_t ired[16];
     __shared__ double dred[16];
+    __shared__ float ax[3];
+    if (g.n > 1) graph_axis(g, t, ax);  // uniform branch
     int64_t m = 0;
     double mv[3] = {0.0, 0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_graph_flip(GraphDesc g, uint32_t t)
             for (int k = 0; k < g.n; ++k) {
                 float v = s[(int64_t)k * g.N + i];
                 if (c) {
-                    v = __fmaf_rn(cf, g.axis[k], v);
+                    v = __fmaf_rn(cf, ax[k], v);
                     s[(int64_t)k * g.N + i] = v;
                 }
                 mv[k] += (double)v;
@@ -418,8 +419,7 @@ hipError_t launch_graph_sweep(const GraphDesc &g, uint32_t t, int slot, hipStrea
 {
     const int nsb = blocks_for(g.N), nbb = blocks_for(g.NB);
     if (g.n > 1) {
-        k_graph_axis<<<1, 64, 0, st>>>(g, t);
-        k_graph_prepare<<<nsb, kBlock, 0, st>>>(g);
+        k_graph_prepare<<<nsb, kBlock, 0, st>>>(g, t);
     }
     k_graph_local<<<blocks_for(g.N, kWindow), kLocalThreads, 0, st>>>(g, t);
     // the cross pass writes no partials (its bond sum goes to an atomic), so
@@ -664,11 +664,11 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     win.shrink_to_fit();
     pos.clear();
     pos.shrink_to_fit();
-    constexpr int kParts = 15;
+    constexpr int kParts = 14;
     size_t off[kParts], total = 0;
     const size_t sizes[kParts] = {sizeof(int32_t) * (size_t)n_bonds, sizeof(int32_t) * (size_t)n_bonds, spin_bytes,
                                   sizeof(int32_t) * (size_t)n_sites, model == PYRO_ISING ? 0 : sizeof(float) * (size_t)n_sites,
-                                  16, sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
+                                  sizeof(int64_t) * 2 * kPartBlocks, sizeof(double) * 4 * kPartBlocks,
                                   sizeof(DevRecord) * (kGraphRing + 1), sizeof(uint32_t) * (size_t)n_bonds,
                                   sizeof(int64_t) * (size_t)(nwin + 1), sizeof(unsigned long long),
                                   sizeof(int32_t) * wsite.size(), sizeof(uint16_t) * (size_t)n_inside,
@@ -704,16 +704,15 @@ int pyro_sw_graph_init(pyro_sw_graph **out, int64_t n_sites, int64_t n_bonds, co
     d.spins = g->mem + off[2];
     d.label = (int32_t *)(g->mem + off[3]);
     d.sigma = model == PYRO_ISING ? nullptr : (float *)(g->mem + off[4]);
-    d.axis = (float *)(g->mem + off[5]);
-    d.ipart = (int64_t *)(g->mem + off[6]);
-    d.dpart = (double *)(g->mem + off[7]);
-    d.ring = (DevRecord *)(g->mem + off[8]);
-    d.bond_id = (const uint32_t *)(g->mem + off[9]);
-    d.wstart = (const int64_t *)(g->mem + off[10]);
-    d.eacc = (unsigned long long *)(g->mem + off[11]);
-    d.wsite = balls ? (const int32_t *)(g->mem + off[12]) : nullptr;
-    d.la = (const uint16_t *)(g->mem + off[13]);
-    d.lb = (const uint16_t *)(g->mem + off[14]);
+    d.ipart = (int64_t *)(g->mem + off[5]);
+    d.dpart = (double *)(g->mem + off[6]);
+    d.ring = (DevRecord *)(g->mem + off[7]);
+    d.bond_id = (const uint32_t *)(g->mem + off[8]);
+    d.wstart = (const int64_t *)(g->mem + off[9]);
+    d.eacc = (unsigned long long *)(g->mem + off[10]);
+    d.wsite = balls ? (const int32_t *)(g->mem + off[11]) : nullptr;
+    d.la = (const uint16_t *)(g->mem + off[12]);
+    d.lb = (const uint16_t *)(g->mem + off[13]);
     d.J = J;
     d.key = philox_key(seed);
     graph_params(g, T);
