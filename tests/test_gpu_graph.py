@@ -69,6 +69,58 @@ def test_simple_cubic_across_windows_equals_oracle(model, L, T):
     g.close()
 
 
+def ball_cut_fewer(n, a, b, window=4096):
+    """The library's window rule, restated: windows grown breadth first from
+    the smallest free site, 4096 sites each, are used when they cut fewer
+    bonds than windows of consecutive indices.  True when they do."""
+    import collections
+    adj = [[] for _ in range(n)]
+    for x, y in zip(a.tolist(), b.tolist()):
+        adj[x].append(y)
+        adj[y].append(x)
+    win = [-1] * n
+    w, fill, nxt, taken = 0, 0, 0, 0
+    while taken < n:
+        while win[nxt] >= 0:
+            nxt += 1
+        q = collections.deque([nxt])
+        win[nxt] = w
+        taken += 1
+        fill += 1
+        full = fill == window
+        while q and not full:
+            x = q.popleft()
+            for y in adj[x]:
+                if win[y] < 0:
+                    win[y] = w
+                    taken += 1
+                    fill += 1
+                    q.append(y)
+                    if fill == window:
+                        full = True
+                        break
+        if full:
+            w, fill = w + 1, 0
+    win = np.asarray(win)
+    return int(np.sum(win[a] != win[b])) < int(np.sum(a // window != b // window))
+
+
+@pytest.mark.parametrize("lattice,model,L,T", [("sc", 1, 48, 4.511524), ("sc", 2, 40, 2.20182),
+                                               ("pyro", 1, 12, 4.2139)])
+def test_breadth_first_windows_equal_oracle(lattice, model, L, T):
+    """Tables that breadth-first windows cut less than consecutive ones (so
+    the window pass gathers its sites through the window's site list): the
+    trajectory is still the oracle's."""
+    say("GPU case: graph path, breadth-first windows, %s L=%d model=%d" % (lattice, L, model))
+    bonds = pyrosw.simple_cubic_bonds(L) if lattice == "sc" else pyrosw.pyro_sw_bonds(L)
+    n = L ** 3 if lattice == "sc" else 16 * L ** 3
+    assert ball_cut_fewer(n, np.asarray(bonds[0], np.int64), np.asarray(bonds[1], np.int64))
+    g = pyrosw.Graph(bonds, n, model, T, seed=90 + L)
+    o = oracle.Oracle(L=L, model=model, T=T, seed=90 + L, start=oracle.RANDOM, lattice=lattice)
+    compare(g, o, 20, model)
+    g.close()
+
+
 def test_pyrochlore_table_across_windows_equals_oracle():
     L, T = 7, 4.2139  # 5488 sites: two windows
     say("GPU case: graph path, pyrochlore table across windows L=%d" % L)
