@@ -388,9 +388,17 @@ int pyro_sw_atomic_rate(int mode, int64_t words, int64_t ops, int repeats, doubl
  *                          ends in range and distinct (EINVAL otherwise);
  *                          host arrays are copied, the caller keeps them;
  *                          model, T, J, seed, start and stream as in
- *                          pyro_sw_init.  One device allocation: 8 B per
- *                          bond, spins, 4 B per site of labels (O(n): 4 more
- *                          of projections), partials, a record ring.
+ *                          pyro_sw_init.  One device allocation: 12 B per
+ *                          bond (ends and table position) and 4 B more per
+ *                          bond inside a 4096-site window, spins, 4 B per
+ *                          site of labels (O(n): 4 more of projections; 4
+ *                          more for the window site lists when the windows
+ *                          are breadth-first balls), partials, a record
+ *                          ring.  The windows are chosen on the host at
+ *                          set-up (a breadth-first pass over the table,
+ *                          about 8 B per bond and 16 B per site of host
+ *                          memory while it runs); they never change a
+ *                          result.
  *   pyro_sw_graph_sweep    enqueue n_sweeps sweeps (records drained to the
  *                          host every 1024 sweeps).
  *   pyro_sw_graph_moments, _get_spins, _set_spins, _get_labels,
