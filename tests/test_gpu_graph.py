@@ -130,7 +130,10 @@ def test_pyrochlore_table_across_windows_equals_oracle():
     g.close()
 
 
-@pytest.mark.parametrize("model,N,NB", [(1, 600, 1800), (2, 600, 1800), (1, 20000, 60000), (3, 20000, 60000)])
+# N = 6000, NB = 40000: a dense graph (mean degree 13) whose first window
+# holds about 21,000 inside bonds
+@pytest.mark.parametrize("model,N,NB", [(1, 600, 1800), (2, 600, 1800), (1, 20000, 60000), (3, 20000, 60000),
+                                        (1, 6000, 40000)])
 def test_random_graph_equals_oracle(model, N, NB):
     rng = np.random.default_rng(9)
     a = rng.integers(0, N, NB)
