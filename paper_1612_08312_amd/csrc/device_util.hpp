@@ -39,6 +39,32 @@ __device__ __forceinline__ T block_sum(T v, T *lds /* >= 16 entries */)
     return s;
 }
 
+// block_sum of N values at once, with one barrier instead of N pairs: each
+// value goes through the same shuffle tree and the same serial sum over the
+// waves as in block_sum, so every result is bit for bit the one block_sum
+// gives.  The sums are valid in thread 0; the kernel's last use of lds.
+template <typename T, int N>
+__device__ __forceinline__ void block_sum_n(T (&v)[N], T *lds /* >= 16 N entries */)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, kWave);
+        if (lane == 0) lds[16 * i + wave] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = T(0);
+            for (int w = 0; w < nw; ++w) s += lds[16 * i + w];
+            v[i] = s;
+        }
+    }
+}
+
 // Block of a tile grid that this workgroup runs.  Consecutive workgroups
 // are dispatched round-robin over the 8 XCDs, each with its own L2; the
 // remap gives each XCD a contiguous run of blocks, i.e. of tiles, which

@@ -307,22 +307,28 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_settle_flip_on(Chain c)
 template <int NV>
 __global__ __launch_bounds__(kFinalizeThreads) void k_finalize_on(Chain c)
 {
-    __shared__ double red[16];
+    __shared__ double red[16 * (1 + NV)];
     const int rep = blockIdx.x;
     const RepState st = *c.state[rep];
     if (st.remaining <= 0) return;
     const RepDesc &d = c.desc[rep];
     const int ntiles = d.ntx * d.nty * d.ntz;
-    double E = 0.0;
-    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) E += d.dpart[k];
-    E = block_sum<double>(E, red);
+    // the energy and the NV magnetisation sums, each in the order of one
+    // block_sum of its own: their loads go out together and one barrier
+    // serves all of them
+    double v[1 + NV];
+#pragma unroll
+    for (int q = 0; q <= NV; ++q) v[q] = 0.0;
+    for (int k = threadIdx.x; k < ntiles; k += blockDim.x) {
+        v[0] += d.dpart[k];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[1 + q] += d.dpart[d.mpart_off * (1 + q) + k];
+    }
+    block_sum_n<double, 1 + NV>(v, red);
+    const double E = v[0];
     double M[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double v = 0.0;
-        for (int k = threadIdx.x; k < ntiles; k += blockDim.x) v += d.dpart[d.mpart_off * (1 + q) + k];
-        M[q] = block_sum<double>(v, red);
-    }
+    for (int q = 0; q < NV; ++q) M[q] = v[1 + q];
     if (threadIdx.x == 0) {
         if (st.e_pending >= 0) d.ring[st.e_pending].E = -d.J * E;
         const int slot = st.ring_used;
