@@ -56,17 +56,17 @@ def bytes_per_site(shape):
 # the probe's 256 MiB copy) and wave instructions (SQ_INSTS_VALU,
 # SQ_INSTS_SALU, SQ_WAVES).  Valid only for the kernel sources they were
 # taken with (fingerprint); the summaries are in profiles/.
-COUNTER_FINGERPRINT = "2cd9442a7c733d60"
+COUNTER_FINGERPRINT = "bce8deb94f4062c8"
 MEASURED_TRAFFIC = {  # kernel -> HBM bytes per launch
-    "local": 216860251,
-    "unite": 194595608,
-    "flip": 269571215,
-    "finalize": 73139,
+    "local": 216857639,
+    "unite": 194594163,
+    "flip": 269545072,
+    "finalize": 73136,
 }
 MEASURED_ISSUE = {  # kernel -> (VALU wave instructions, SALU wave instructions, waves) per launch
-    "local": (62134656, 28267301, 32768),
-    "unite": (11533229, 12804377, 16384),
-    "flip": (24888704, 10495926, 32768),
+    "local": (62134795, 28267641, 32768),
+    "unite": (11532870, 12803987, 16384),
+    "flip": (24889449, 10496674, 32768),
 }
 
 # Issue ceiling of the vector ALUs: a wave64 VALU instruction occupies a
